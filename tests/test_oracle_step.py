@@ -1,0 +1,243 @@
+"""Whole-step pins of the CPU oracle: invariants the paper states or the
+mathematics fixes (free-stream preservation, discrete conservation, D4 symmetry,
+translation by whole cells, fluid-at-rest reduction, closed-form feet), the
+centre-recovery round trip, error statuses, and the linearized step against the
+independent Fourier symbol (which reproduces the paper's printed numbers)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2605_12915_amd import inputs as I
+
+G = 1.4
+
+
+def test_centre_recovery_simpson_roundtrip(orc):
+    """Tensor Simpson of U at the nine Q2 nodes (with the recovered centre) returns
+    the cell average (Sec. 2, eq. center-node)."""
+    P = I.random_smooth(12, 10, seed=1, amp=0.2)
+    s = P.state()
+    C = orc.centres(s, P.h, G)
+    U = lambda r, u, v, p: np.stack([r, r * u, r * v, p / (G - 1) + 0.5 * r * (u * u + v * v)])
+    Vn = lambda di, dj: np.roll(np.roll(s[4:8], -dj, axis=1), -di, axis=2)
+    Evn = lambda di: np.roll(s[8:12], -di, axis=2)
+    Ehn = lambda dj: np.roll(s[12:16], -dj, axis=1)
+    tot = (U(*Vn(0, 0)) + U(*Vn(1, 0)) + U(*Vn(0, 1)) + U(*Vn(1, 1))) / 36 \
+        + (U(*Ehn(0)) + U(*Ehn(1)) + U(*Evn(0)) + U(*Evn(1))) / 9 + 4 * U(*C) / 9
+    np.testing.assert_allclose(tot, s[0:4], rtol=1e-14, atol=1e-14)
+
+
+def test_free_stream_preserved(orc):
+    """Sec. 4: uniform states are preserved (all increments vanish)."""
+    P = I.uniform(8, W=(1.3, 0.7, -0.4, 0.9), ny=6)
+    s = P.state()
+    dt = P.dt_for_cfl(0.45)
+    out = orc.run(s, P.h, G, dt, 100)
+    assert np.max(np.abs(out - s) / np.abs(s).max(axis=(1, 2), keepdims=True)) <= 1e-14
+
+
+def test_conservation(orc):
+    """Sec. 3: the flux-difference average update conserves the totals."""
+    P = I.random_smooth(16, 12, seed=3, amp=0.2)
+    s = P.state()
+    dt = P.dt_for_cfl(0.4)
+    out = orc.run(s, P.h, G, dt, 20)
+    for k in range(4):
+        assert abs(out[k].sum() - s[k].sum()) <= 1e-13 * np.abs(s[k]).sum()
+
+
+def _mirror_x(s):
+    """Reflection x -> -x about a vertex column (n even, centre at x_{n/2})."""
+    n = s.shape[2]
+    out = np.empty_like(s)
+    iv = (-np.arange(n)) % n             # V_i, Ev_i -> index n - i
+    ic = (n - 1 - np.arange(n)) % n      # cells, Eh_i -> index n-1-i
+    out[0:4] = s[0:4][:, :, ic]
+    out[4:8] = s[4:8][:, :, iv]
+    out[8:12] = s[8:12][:, :, iv]
+    out[12:16] = s[12:16][:, :, ic]
+    for b in (1, 5, 9, 13):              # x-momentum / u flips sign
+        out[b] = -out[b]
+    return out
+
+
+def _transpose_xy(s):
+    """Reflection x <-> y: V_ij <-> V_ji, Ev_ij <-> Eh_ji, u <-> v."""
+    out = np.empty_like(s)
+    T = lambda a: np.transpose(a, (0, 2, 1))
+    out[0:4] = T(s[[0, 2, 1, 3]])
+    out[4:8] = T(s[[4, 6, 5, 7]])
+    out[8:12] = T(s[[12, 14, 13, 15]])
+    out[12:16] = T(s[[8, 10, 9, 11]])
+    return out
+
+
+def test_d4_symmetry_of_centred_pulse(orc):
+    """Sec. 6.3: the radially symmetric pulse stays symmetric; the discrete scheme is
+    exactly equivariant under the grid's symmetry group (to round-off)."""
+    P = I.paper_pulse(16)
+    s = P.state()
+    np.testing.assert_allclose(_mirror_x(s), s, atol=1e-15)
+    np.testing.assert_allclose(_transpose_xy(s), s, atol=1e-15)
+    dt = P.dt_for_cfl(0.475)
+    out = orc.run(s, P.h, G, dt, 12)
+    scale = np.abs(out).max()
+    assert np.max(np.abs(_mirror_x(out) - out)) < 1e-14 * scale
+    assert np.max(np.abs(_transpose_xy(out) - out)) < 1e-14 * scale
+
+
+def test_equivariance_random(orc):
+    """Mirror and transpose commute with the step for arbitrary moving data."""
+    P = I.random_smooth(10, 10, seed=5, amp=0.2, vel=(0.4, 0.25))
+    s = P.state()
+    dt = P.dt_for_cfl(0.4)
+    a = orc.step(_mirror_x(s), P.h, G, dt)
+    b = _mirror_x(orc.step(s, P.h, G, dt))
+    np.testing.assert_allclose(a, b, rtol=0, atol=2e-14 * np.abs(b).max())
+    a = orc.step(_transpose_xy(s), P.h, G, dt)
+    b = _transpose_xy(orc.step(s, P.h, G, dt))
+    np.testing.assert_allclose(a, b, rtol=0, atol=2e-14 * np.abs(b).max())
+
+
+def test_translation_by_whole_cells_bitwise(orc):
+    P = I.random_smooth(12, 8, seed=7, amp=0.2, vel=(0.5, -0.3))
+    s = P.state()
+    dt = P.dt_for_cfl(0.4)
+    sh = np.roll(np.roll(s, 3, axis=2), -2, axis=1)
+    a = orc.run(sh, P.h, G, dt, 3)
+    b = np.roll(np.roll(orc.run(s, P.h, G, dt, 3), 3, axis=2), -2, axis=1)
+    assert np.array_equal(a, b)
+
+
+def test_fluid_at_rest_reduces_to_acoustics(orc):
+    """With u = v = 0 the feet are the nodes, so the transported update is the pure
+    node acoustic update with density from the frozen invariant (Sec. 3.1)."""
+    P = I.gaussian_pulse(12, amp=0.2, width=0.2)
+    s = P.state()
+    tau = 0.4 * P.h / 1.2
+    ft, pts, st = orc.feet(s, P.h, G, tau)
+    assert st == 0
+    assert np.abs(ft).max() == 0.0
+    inc, _ = orc.increments(s, P.h, G, tau, threads=1)
+    for fam in range(3):
+        W = s[4 + 4 * fam: 8 + 4 * fam]
+        du, dv, dp = inc[fam]
+        c2 = G * W[3] / W[0]
+        want = np.stack([W[0] + dp / c2, W[1] + du, W[2] + dv, W[3] + dp])
+        np.testing.assert_allclose(pts[fam], want, rtol=0, atol=1e-15)
+
+
+def test_feet_uniform_velocity(orc):
+    P = I.uniform(6, W=(1.0, 0.37, -0.21, 1.0))
+    s = P.state()
+    tau = 0.7 * P.h
+    ft, _, st = orc.feet(s, P.h, G, tau)
+    assert st == 0
+    np.testing.assert_allclose(ft[:, 0], -0.37 * tau / P.h, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(ft[:, 1], 0.21 * tau / P.h, rtol=0, atol=1e-15)
+
+
+def test_feet_linear_velocity(orc):
+    """Two-Picard foot (eq. adv-footpoint) for an affine velocity field u = a + B x:
+    P1 = P - tau u(P), Pf = P - tau u(P1).  The Q2 reconstruction of affine data is
+    exact, so the oracle's feet at interior nodes must match this closed form."""
+    n = 12
+    a = np.array([0.3, -0.2])
+    B = np.array([[0.02, -0.03], [0.015, 0.01]])
+    s = np.zeros((16, n, n))
+    Ii, Jj = np.meshgrid(np.arange(n, dtype=float), np.arange(n, dtype=float))
+    vel = lambda X, Y: (a[0] + B[0, 0] * X + B[0, 1] * Y, a[1] + B[1, 0] * X + B[1, 1] * Y)
+    for base, dx, dy in ((4, 0, 0), (8, 0, 0.5), (12, 0.5, 0)):
+        u, v = vel(Ii + dx, Jj + dy)
+        s[base:base + 4] = np.stack([np.ones_like(u), u, v, np.ones_like(u)])
+    uc, vc = vel(Ii + 0.5, Jj + 0.5)
+    wq = np.array([1, 4, 1]) / 6
+    for k, fn in enumerate((lambda u, v: 1.0 + 0 * u, lambda u, v: u, lambda u, v: v,
+                            lambda u, v: 1 / (G - 1) + 0.5 * (u * u + v * v))):
+        acc = 0.0
+        for ia in range(3):
+            for ib in range(3):
+                u, v = vel(Ii + 0.5 * ia, Jj + 0.5 * ib)
+                acc = acc + wq[ia] * wq[ib] * fn(u, v)
+        s[k] = acc
+    tau = 0.8
+    ft, _, st = orc.feet(s, 1.0, G, tau)
+    for fam, (ox, oy) in enumerate(((0, 0), (0, 0.5), (0.5, 0))):
+        for j in range(3, n - 3):
+            for i in range(3, n - 3):
+                Pp = np.array([i + ox, j + oy])
+                P1 = Pp - tau * np.array(vel(*Pp))
+                Pf = Pp - tau * np.array(vel(*P1))
+                np.testing.assert_allclose(ft[fam, :, j, i], Pf - Pp, rtol=0, atol=1e-14)
+
+
+def test_status_codes(orc):
+    P = I.uniform(6, W=(1.0, 0.1, 0.0, 1.0))
+    s = P.state()
+    c = math.sqrt(G)
+    _, st = orc.step(s, P.h, G, 0.51 * P.h / c, check=False)
+    assert st == 1            # acoustic CFL
+    bad = s.copy()
+    bad[7, 2, 3] = -1.0       # negative vertex pressure
+    _, st = orc.step(bad, P.h, G, 0.1 * P.h, check=False)
+    assert st == 3
+    P = I.uniform(6, W=(1.0, 3.0, 0.0, 0.01))
+    s = P.state()
+    _, st = orc.step(s, P.h, G, 0.4 * P.h, check=False)
+    assert st == 2            # foot beyond one cell (|u| dt / h = 1.2)
+
+
+# ---------------------------------------------------------------------------
+# Linearized step vs the Fourier symbol (complex-step JVP, exact to round-off)
+# ---------------------------------------------------------------------------
+
+def _cons_jac(W):
+    r, u, v, p = W
+    return np.array([[1, 0, 0, 0], [u, r, 0, 0], [v, 0, r, 0],
+                     [0.5 * (u * u + v * v), r * u, r * v, 1 / (G - 1)]])
+
+
+@pytest.mark.parametrize("method,scheme,nu", [("TAI", 0, 0.25), ("TAI", 0, 0.45), ("RB", 1, 0.15)])
+def test_single_mode_matches_symbol(orc, method, scheme, nu):
+    from oracle.symbol import Symbol
+    W0 = (1.0, 0.2 * math.cos(math.radians(25)), 0.2 * math.sin(math.radians(25)), 1.0)
+    sym = Symbol(W0, G)
+    n = 8
+    h = 1.0 / n
+    dt = nu * h / sym.c0
+    base = I.uniform(n, W=W0).state()
+    J = _cons_jac(W0)
+    Jinv = np.linalg.inv(J)
+    rng = np.random.default_rng(17)
+    for kx, ky in ((1, 0), (2, 3), (-3, 1), (4, 4)):
+        xi, eta = 2 * math.pi * kx / n, 2 * math.pi * ky / n
+        q = rng.normal(size=16) + 1j * rng.normal(size=16)
+        jj, ii = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+        ph = np.exp(1j * (xi * ii + eta * jj))
+        field = q[:, None, None] * ph[None]                     # primitive families
+        d = np.real(field).copy()
+        d[0:4] = np.einsum("ab,bij->aij", J, np.real(field[0:4]))
+        _, jv = orc.step_jvp(base, d, h, G, dt, scheme=scheme)
+        jv[0:4] = np.einsum("ab,bij->aij", Jinv, jv[0:4])
+        want = np.real((sym.G(method, nu, xi, eta) @ q)[:, None, None] * ph[None])
+        np.testing.assert_allclose(jv, want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+# ---------------------------------------------------------------------------
+# Convergence (Sec. 6.2): isentropic vortex, one period, CFL 0.3
+# ---------------------------------------------------------------------------
+
+@pytest.mark.slow
+def test_vortex_third_order(orc):
+    errs = []
+    ns = (16, 32, 64)
+    for n in ns:
+        P = I.isentropic_vortex(n, L=10.0, center=(5.0, 0.0), uinf=(1.0, 0.0), y0=-5.0)
+        s = P.state()
+        dt0 = P.dt_for_cfl(0.3)
+        nsteps = int(math.ceil(10.0 / dt0))
+        out = orc.run(s, P.h, G, 10.0 / nsteps, nsteps)
+        errs.append(math.sqrt(np.mean((out[0] - s[0]) ** 2)))
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(len(ns) - 1)]
+    assert min(orders) > 2.6, (errs, orders)
