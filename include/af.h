@@ -1,0 +1,137 @@
+/*
+ * af.h -- C ABI of the MI355X (gfx950) fully discrete Active Flux library:
+ * the RB-TAI time step of Duraisamy, "Fully Discrete Active Flux Method based on
+ * Transported Acoustic Increments for the Compressible Euler Equations".
+ *
+ * Problem (Sec. 2): 2-D compressible Euler, ideal gas, periodic Cartesian grid of
+ * nx x ny square cells of side h.  Cell C_ij = [x_i, x_{i+1}] x [y_j, y_{j+1}].
+ *
+ * State (Sec. 2, list of degrees of freedom; Fig. 1): 16 planes of nx*ny scalars,
+ * row-major with i (x) fastest, element (i, j) at offset j*nx + i:
+ *   avg[0..3] = conservative cell averages (rho, rho u, rho v, E) of C_ij,
+ *   V[0..3]   = primitive (rho, u, v, p) at the vertex (x_i, y_j),
+ *   EV[0..3]  = primitive at the vertical-edge midpoint (x_i, y_{j+1/2}),
+ *   EH[0..3]  = primitive at the horizontal-edge midpoint (x_{i+1/2}, y_j).
+ * Element type: double for AF_F64 contexts; for AF_F32 contexts float
+ * perturbations about the context's background state (see af_config.bg).
+ * All state pointers are DEVICE pointers owned by the caller.
+ *
+ * Every function returns an af_status; none aborts or prints.  Work is enqueued on
+ * the HIP stream given to af_init (borrowed, not owned) and is asynchronous unless
+ * stated otherwise.
+ */
+#ifndef AF_H_
+#define AF_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t af_status;
+
+enum {
+    AF_OK = 0,
+    AF_ERR_ARG = 1,          /* null pointer, nx < 4 or ny < 4, h <= 0, gamma <= 1, bad dt */
+    AF_ERR_HIP = 2,          /* HIP runtime error; af_last_hip_error() returns its code */
+    AF_ERR_ACOUSTIC_CFL = 3, /* some node has c_K dt / h > 1/2 (node-centred wedges invalid) */
+    AF_ERR_FOOT = 4,         /* some convective foot moved one cell or more */
+    AF_ERR_NONPHYSICAL = 5,  /* rho <= 0 or p <= 0 at a node or recovered centre, or NaN */
+    AF_ERR_UNSUPPORTED = 6   /* operation not available for this context's precision */
+};
+
+enum { AF_F64 = 0, AF_F32 = 1 };
+
+enum {
+    AF_CHECK = 1,       /* af_step reads back the device status flag after each call
+                           (one host synchronisation per call) and returns the error */
+    AF_SCHEME_RB = 2    /* additive RB point update (eq. barsukow-additive) instead of
+                           the transported-increment update (eq. transported-update) */
+};
+
+typedef struct af_config {
+    int32_t nx, ny;      /* cells in x and y (>= 4) */
+    double x0, y0;       /* lower-left corner (informational) */
+    double h;            /* cell size, dx = dy = h (Sec. 2) */
+    double gamma;        /* ratio of specific heats (> 1) */
+    int32_t precision;   /* AF_F64 or AF_F32 */
+    double bg[4];        /* AF_F32: background primitive state (rho, u, v, p) about which
+                            the float planes hold perturbations; ignored for AF_F64 */
+    int32_t flags;       /* AF_CHECK | AF_SCHEME_RB */
+} af_config;
+
+typedef struct af_state {
+    void* avg[4];
+    void* V[4];
+    void* EV[4];
+    void* EH[4];
+} af_state;
+
+typedef struct af_diag {
+    double mass, momx, momy, energy; /* h^2 * sum over cells of the averages */
+    double entropy;                  /* -int rho log(p / rho^gamma) dA, tensor Simpson
+                                        over the nine Q2 nodes of every cell */
+    double min_rho, min_p;           /* over V, EV, EH nodes and recovered centres */
+    double max_speed;                /* max(|u| + c) over the same nodes */
+    double max_acoustic_r;           /* max c dt / h over the same nodes, for dt given */
+} af_diag;
+
+typedef struct af_ctx af_ctx;
+
+/* Create a context for one grid.  cfg is copied.  hip_stream: a hipStream_t (may be
+ * NULL for the null stream), borrowed for the life of the context.  Allocates the
+ * context's device scratch (a second state for ping-ponging, reduction buffers, the
+ * status flag) on the current device.  *out receives the context. */
+af_status af_init(const af_config* cfg, void* hip_stream, af_ctx** out);
+
+/* Advance nsteps >= 1 steps of size dt (fixed) in place.  Each step is the algorithm
+ * of Sec. 6.1: centre recovery (eq. center-node), node-centred exact acoustic
+ * increments at V, EV, EH and recovered centres for tau = dt/2 and dt (App. D,
+ * eq. compact-monomial-block), cellwise Q2 interpolants of the increments, the
+ * two-Picard convective foot (eq. adv-footpoint), the transported point update
+ * (eq. transported-update; density from the frozen invariant), space-time Simpson
+ * fluxes and the conservative average update (eq. af-average-update).
+ * inout: caller-owned device planes, overwritten with the state after nsteps.
+ * Errors: AF_ERR_ARG for a bad dt (<= 0 or not finite); with AF_CHECK set, the
+ * acoustic-CFL, foot and non-physical checks are read back after the call and, if
+ * one fired, *inout is left at the state before the failing call.  Without AF_CHECK
+ * the flag is only accumulated on the device (read it with af_read_status). */
+af_status af_step(af_ctx* ctx, af_state* inout, double dt, int32_t nsteps);
+
+/* One step from `in` to `out` (distinct buffers, both caller-owned); same operation
+ * and errors as af_step with nsteps = 1, except that `in` is never modified. */
+af_status af_step_out(af_ctx* ctx, const af_state* in, af_state* out, double dt);
+
+/* Read and clear the device status flag accumulated since the last read
+ * (synchronises the stream).  *status receives AF_OK or the first error class. */
+af_status af_read_status(af_ctx* ctx, af_status* status);
+
+/* Reverse-mode derivative of one step (AF_F64 only): cot_n = (d step / d state_n)^T
+ * cot_np1 at fixed dt, where step is the map of af_step_out.  primal_n: the state the
+ * step was taken from; cot_np1: cotangent of the step's output; cot_n: overwritten
+ * (not accumulated).  All three are caller-owned device states of doubles. */
+af_status af_step_adjoint(af_ctx* ctx, const af_state* primal_n, const af_state* cot_np1,
+                          af_state* cot_n, double dt);
+
+/* Diagnostics of a state (Sec. 6, opening paragraph: CFL and entropy; Sec. 3:
+ * conservation), reduced in FP64 on the device.  Synchronous: returns when *out is
+ * filled.  dt only enters max_acoustic_r. */
+af_status af_diagnostics(af_ctx* ctx, const af_state* s, double dt, af_diag* out);
+
+/* Time the step kernel(s): runs nsteps steps on a scratch copy of `s` bracketed by
+ * HIP events recorded on the context stream and returns the elapsed milliseconds of
+ * the whole sequence and of the dominant kernel's launches (sum).  `s` is unchanged. */
+af_status af_time_steps(af_ctx* ctx, const af_state* s, double dt, int32_t nsteps,
+                        double* total_ms, double* kernel_ms);
+
+void af_destroy(af_ctx* ctx);
+const char* af_status_string(af_status s);
+int32_t af_last_hip_error(void);
+/* Name of the kernel af_time_steps reports as dominant. */
+const char* af_dominant_kernel(af_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AF_H_ */

@@ -1,0 +1,122 @@
+// FP64 diagnostics of a state (Sec. 6 opening paragraph: CFL and the entropy
+// functional -int rho log(p / rho^gamma) dA; Sec. 3: conservation totals).
+// Two passes: a grid-stride block reduction into per-block partials (wavefront
+// shuffles, then LDS across the block's wavefronts), then one block over the
+// partials.  Entropy uses the tensor Simpson rule over the nine Q2 nodes of a cell
+// (the recovered centre included).
+#include <hip/hip_runtime.h>
+
+#include "af_internal.h"
+#include "af_kernels.h"
+
+namespace af {
+
+constexpr int kDiagVals = 9;   // 5 sums, min rho, min p, max(|u|+c), max c
+constexpr int kDiagBlock = 256;
+
+__device__ __forceinline__ void combine(double* a, const double* b) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) a[k] += b[k];
+    a[5] = fmin(a[5], b[5]);
+    a[6] = fmin(a[6], b[6]);
+    a[7] = fmax(a[7], b[7]);
+    a[8] = fmax(a[8], b[8]);
+}
+
+__device__ __forceinline__ void block_reduce(double v[kDiagVals], double* sh) {
+    // within the wavefront
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        double o[kDiagVals];
+#pragma unroll
+        for (int k = 0; k < kDiagVals; ++k) o[k] = __shfl_down(v[k], off, 64);
+        combine(v, o);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < kDiagVals; ++k) sh[wid * kDiagVals + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) combine(v, sh + w * kDiagVals);
+    }
+}
+
+struct DiagAcc {
+    const double* s[16];
+    const double* dummyC;
+    int nx, ny;
+    double gamma;
+    __device__ __forceinline__ size_t idx(int i, int j) const {
+        i = i >= nx ? i - nx : i;
+        j = j >= ny ? j - ny : j;
+        return (size_t)j * nx + i;
+    }
+    __device__ __forceinline__ Prim<double> node(int fam, int i, int j) const {
+        size_t k = idx(i, j);
+        if (fam == F_C) {
+            double Ub[4] = {s[0][k], s[1][k], s[2][k], s[3][k]};
+            return recover_centre(Ub, node(F_V, i, j), node(F_V, i + 1, j), node(F_V, i, j + 1),
+                                  node(F_V, i + 1, j + 1), node(F_EH, i, j), node(F_EH, i, j + 1),
+                                  node(F_EV, i, j), node(F_EV, i + 1, j), gamma);
+        }
+        const int b = 4 + 4 * fam;
+        return {s[b][k], s[b + 1][k], s[b + 2][k], s[b + 3][k]};
+    }
+};
+
+__global__ void __launch_bounds__(kDiagBlock) k_diag(StatePtrs<const double> st, int nx, int ny, double gamma,
+                                                     double* partials) {
+    __shared__ double sh[(kDiagBlock / 64) * kDiagVals];
+    DiagAcc A{{}, nullptr, nx, ny, gamma};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) A.s[k] = st.p[k];
+    double v[kDiagVals] = {0, 0, 0, 0, 0, 1e300, 1e300, 0, 0};
+    const size_t N = (size_t)nx * ny;
+    const double wq[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(c % nx), j = (int)(c / nx);
+        for (int k = 0; k < 4; ++k) v[k] += st.p[k][c];
+        Prim<double> n[3][3];
+        cell_nodes<double>(A, i, j, n);
+        double e = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                const Prim<double>& w = n[a][b];
+                e += wq[a] * wq[b] * w.r * log(w.p / pow(w.r, gamma));
+            }
+        v[4] -= e;
+        const Prim<double> own[4] = {n[0][0], n[0][1], n[1][0], n[1][1]};   // V, EV, EH, C of cell (i,j)
+        for (int f = 0; f < 4; ++f) {
+            const Prim<double>& w = own[f];
+            double cs = sqrt(gamma * w.p / w.r);
+            v[5] = fmin(v[5], w.r);
+            v[6] = fmin(v[6], w.p);
+            v[7] = fmax(v[7], sqrt(w.u * w.u + w.v * w.v) + cs);
+            v[8] = fmax(v[8], cs);
+        }
+    }
+    block_reduce(v, sh);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kDiagVals; ++k) partials[(size_t)blockIdx.x * kDiagVals + k] = v[k];
+}
+
+__global__ void __launch_bounds__(kDiagBlock) k_diag_final(const double* partials, int n, double* out) {
+    __shared__ double sh[(kDiagBlock / 64) * kDiagVals];
+    double v[kDiagVals] = {0, 0, 0, 0, 0, 1e300, 1e300, 0, 0};
+    for (int b = threadIdx.x; b < n; b += blockDim.x) combine(v, partials + (size_t)b * kDiagVals);
+    block_reduce(v, sh);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kDiagVals; ++k) out[k] = v[k];
+}
+
+hipError_t launch_diag_f64(const void* const s[16], int nx, int ny, double h, double gamma, double* partials,
+                           int npartials, double* out9, hipStream_t stream) {
+    StatePtrs<const double> st;
+    for (int k = 0; k < 16; ++k) st.p[k] = (const double*)s[k];
+    hipLaunchKernelGGL(k_diag, dim3(npartials), dim3(kDiagBlock), 0, stream, st, nx, ny, gamma, partials);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagBlock), 0, stream, partials, npartials, out9);
+    return hipGetLastError();
+}
+
+}  // namespace af

@@ -1,0 +1,33 @@
+// Internal host/device interface between the C ABI layer and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace af {
+
+enum StatusBits { SB_CFL = 1, SB_FOOT = 2, SB_NONPHYS = 4 };
+
+template <class T>
+struct StatePtrs { T* p[16]; };
+
+struct StepArgs {
+    int nx, ny;
+    double h, gamma, dt;
+    int scheme;                 // 0: transported increments, 1: additive RB
+    void* in[16];
+    void* out[16];
+    void* scratch;              // path-specific device scratch
+    unsigned* status;           // device status bits (atomicOr)
+    hipStream_t stream;
+    hipEvent_t ev_begin, ev_end;  // optional: recorded around the dominant kernel
+    int variant;                // kernel variant (path-specific)
+};
+
+hipError_t launch_step_multi_f64(const StepArgs& a);
+size_t scratch_bytes_multi_f64(int nx, int ny);
+
+hipError_t launch_diag_f64(const void* const s[16], int nx, int ny, double h, double gamma, double* partials,
+                           int npartials, double* out9, hipStream_t stream);
+
+}  // namespace af

@@ -1,0 +1,120 @@
+"""PyTorch-facing wrapper of the C ABI.  Torch provides device memory and the stream
+only; the step, its adjoint and the diagnostics run in libaf.so's HIP kernels.
+
+A state is a (16, ny, nx) tensor on the GPU in the plane layout of include/af.h:
+[avg(rho, rho u, rho v, E), V(rho,u,v,p), EV(...), EH(...)], x fastest.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import AF_CHECK, AF_F32, AF_F64, AF_SCHEME_RB, AfConfig, AfDiag, AfState, check
+
+
+def state_struct(t: torch.Tensor) -> AfState:
+    if t.dim() != 3 or t.shape[0] != 16 or not t.is_contiguous():
+        raise ValueError("state must be a contiguous (16, ny, nx) tensor")
+    if not t.is_cuda:
+        raise ValueError("state must live on the GPU")
+    s = AfState()
+    base = t.data_ptr()
+    stride = t.stride(0) * t.element_size()
+    for k in range(4):
+        s.avg[k] = base + k * stride
+        s.V[k] = base + (4 + k) * stride
+        s.EV[k] = base + (8 + k) * stride
+        s.EH[k] = base + (12 + k) * stride
+    return s
+
+
+class Stepper:
+    """One grid (nx, ny, h, gamma) bound to a HIP stream."""
+
+    def __init__(self, nx: int, ny: int, h: float, gamma: float = 1.4, precision: str = "f64",
+                 scheme: str = "tai", check_errors: bool = False, bg: Sequence[float] = (1.0, 0.0, 0.0, 1.0),
+                 x0: float = 0.0, y0: float = 0.0, stream: Optional[torch.cuda.Stream] = None,
+                 device: Optional[torch.device] = None):
+        L = _lib.lib()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        cfg = AfConfig()
+        cfg.nx, cfg.ny, cfg.x0, cfg.y0, cfg.h, cfg.gamma = nx, ny, x0, y0, h, gamma
+        cfg.precision = AF_F64 if precision == "f64" else AF_F32
+        for k in range(4):
+            cfg.bg[k] = float(bg[k])
+        cfg.flags = (AF_CHECK if check_errors else 0) | (AF_SCHEME_RB if scheme == "rb" else 0)
+        self.cfg = cfg
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        self._ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(L.af_init(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._ctx)),
+                  "af_init")
+
+    def close(self):
+        if self._ctx and self._ctx.value:
+            _lib.lib().af_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_state(self, t: torch.Tensor):
+        if t.dtype != self.dtype or tuple(t.shape) != (16, self.cfg.ny, self.cfg.nx):
+            raise ValueError(f"expected a (16, {self.cfg.ny}, {self.cfg.nx}) {self.dtype} tensor")
+        if t.device != self.device:
+            raise ValueError("state on the wrong device")
+
+    def step(self, state: torch.Tensor, dt: float, nsteps: int = 1) -> torch.Tensor:
+        """Advance in place; returns `state`."""
+        self._check_state(state)
+        s = state_struct(state)
+        check(_lib.lib().af_step(self._ctx, ctypes.byref(s), float(dt), int(nsteps)), "af_step")
+        return state
+
+    def step_out(self, state: torch.Tensor, dt: float, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._check_state(state)
+        out = torch.empty_like(state) if out is None else out
+        self._check_state(out)
+        a, b = state_struct(state), state_struct(out)
+        check(_lib.lib().af_step_out(self._ctx, ctypes.byref(a), ctypes.byref(b), float(dt)), "af_step_out")
+        return out
+
+    def read_status(self) -> int:
+        st = ctypes.c_int32()
+        check(_lib.lib().af_read_status(self._ctx, ctypes.byref(st)), "af_read_status")
+        return st.value
+
+    def adjoint(self, primal: torch.Tensor, cot_next: torch.Tensor, dt: float,
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        for t in (primal, cot_next):
+            self._check_state(t)
+        out = torch.empty_like(primal) if out is None else out
+        a, b, c = state_struct(primal), state_struct(cot_next), state_struct(out)
+        check(_lib.lib().af_step_adjoint(self._ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), float(dt)),
+              "af_step_adjoint")
+        return out
+
+    def diagnostics(self, state: torch.Tensor, dt: float = 0.0) -> dict:
+        self._check_state(state)
+        s = state_struct(state)
+        d = AfDiag()
+        check(_lib.lib().af_diagnostics(self._ctx, ctypes.byref(s), float(dt), ctypes.byref(d)), "af_diagnostics")
+        return d.as_dict()
+
+    def time_steps(self, state: torch.Tensor, dt: float, nsteps: int):
+        self._check_state(state)
+        s = state_struct(state)
+        tot, ker = ctypes.c_double(), ctypes.c_double()
+        check(_lib.lib().af_time_steps(self._ctx, ctypes.byref(s), float(dt), int(nsteps), ctypes.byref(tot),
+                                       ctypes.byref(ker)), "af_time_steps")
+        return tot.value, ker.value
+
+    def dominant_kernel(self) -> str:
+        return _lib.lib().af_dominant_kernel(self._ctx).decode()
