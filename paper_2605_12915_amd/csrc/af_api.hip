@@ -2,8 +2,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "af.h"
 #include "af_internal.h"
@@ -28,7 +30,8 @@ struct af_ctx {
     unsigned* status;      // device status bits
     double* partials;      // diagnostics partials
     double* diag_out;      // 9 doubles on the device
-    hipEvent_t ev[4];
+    hipEvent_t ev[4];      // [0], [1]: owned; [2], [3]: slots for per-launch timing events
+    int variant;           // 0: fused LDS-tiled kernel, 1: multi-kernel path
 };
 
 #define AF_HIP(x)                                       \
@@ -85,8 +88,9 @@ hipError_t launch_step(af_ctx* c, void* const in[16], void* const out[16], doubl
     a.stream = c->stream;
     a.ev_begin = timed ? c->ev[2] : nullptr;
     a.ev_end = timed ? c->ev[3] : nullptr;
-    a.variant = 0;
-    return af::launch_step_multi_f64(a);
+    a.variant = c->variant;
+    if (c->variant == 1) return af::launch_step_multi_f64(a);
+    return af::launch_step_fused_f64(a);
 }
 
 hipError_t copy_state(af_ctx* c, void* const dst[16], void* const src[16]) {
@@ -140,13 +144,16 @@ af_status af_init(const af_config* cfg, void* hip_stream, af_ctx** out) {
     c->N = (size_t)cfg->nx * cfg->ny;
     c->elem = sizeof(double);
     hipError_t e = hipGetDevice(&c->device);
-    size_t sbytes = af::scratch_bytes_multi_f64(cfg->nx, cfg->ny);
+    const char* v = getenv("AF_VARIANT");
+    c->variant = (v && std::strcmp(v, "multi") == 0) ? 1 : 0;
+    size_t sbytes = c->variant == 1 ? af::scratch_bytes_multi_f64(cfg->nx, cfg->ny) : 16;
+    if (e == hipSuccess && c->variant == 0) e = af::prepare_fused_f64();
     if (e == hipSuccess) e = hipMalloc(&c->state2, 16 * c->N * c->elem);
     if (e == hipSuccess) e = hipMalloc(&c->scratch, sbytes);
     if (e == hipSuccess) e = hipMalloc((void**)&c->status, sizeof(unsigned));
     if (e == hipSuccess) e = hipMalloc((void**)&c->partials, kDiagPartials * 9 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&c->diag_out, 9 * sizeof(double));
-    for (int k = 0; k < 4 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
     if (e == hipSuccess) e = hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -168,7 +175,7 @@ void af_destroy(af_ctx* c) {
     if (c->status) (void)hipFree(c->status);
     if (c->partials) (void)hipFree(c->partials);
     if (c->diag_out) (void)hipFree(c->diag_out);
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 2; ++k)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     delete c;
 }
@@ -252,39 +259,52 @@ af_status af_diagnostics(af_ctx* c, const af_state* s, double dt, af_diag* out) 
 
 af_status af_time_steps(af_ctx* c, const af_state* s, double dt, int32_t nsteps, double* total_ms,
                         double* kernel_ms) {
-    if (!c || !state_ok(s) || nsteps < 1 || !total_ms || !kernel_ms || !(dt > 0.0)) return AF_ERR_ARG;
+    if (!c || !state_ok(s) || nsteps < 1 || nsteps > 4096 || !total_ms || !kernel_ms || !(dt > 0.0))
+        return AF_ERR_ARG;
     if (!c->state3) AF_HIP(hipMalloc(&c->state3, 16 * c->N * c->elem));
     void *src[16], *a[16], *b[16];
     planes_of(s, src);
     planes_of_buffer(c->state3, c->N, c->elem, a);
     planes_of_buffer(c->state2, c->N, c->elem, b);
     AF_HIP(copy_state(c, a, src));
-    double ksum = 0.0;
-    AF_HIP(hipEventRecord(c->ev[0], c->stream));
-    for (int k = 0; k < nsteps; ++k) {
+    // one event pair around every launch of the dominant kernel, on the context stream
+    std::vector<hipEvent_t> ev(2 * (size_t)nsteps, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto& x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    if (e == hipSuccess) e = hipEventRecord(c->ev[0], c->stream);
+    for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
         void** x = (k & 1) ? b : a;
         void** y = (k & 1) ? a : b;
-        AF_HIP(launch_step(c, x, y, dt, true));
+        c->ev[2] = ev[2 * k];
+        c->ev[3] = ev[2 * k + 1];
+        e = launch_step(c, x, y, dt, true);
     }
-    AF_HIP(hipEventRecord(c->ev[1], c->stream));
-    AF_HIP(hipEventSynchronize(c->ev[1]));
+    c->ev[2] = c->ev[3] = nullptr;
+    if (e == hipSuccess) e = hipEventRecord(c->ev[1], c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(c->ev[1]);
     float ms = 0.f;
-    AF_HIP(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    double ksum = 0.0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
     *total_ms = ms;
-    // the dominant kernel: one more timed step with events around it alone
-    (void)ksum;
-    AF_HIP(hipEventRecord(c->ev[2], c->stream));
-    AF_HIP(launch_step(c, a, b, dt, false));
-    AF_HIP(hipEventRecord(c->ev[3], c->stream));
-    AF_HIP(hipEventSynchronize(c->ev[3]));
-    AF_HIP(hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
-    *kernel_ms = ms;
+    for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
+        float km = 0.f;
+        e = hipEventElapsedTime(&km, ev[2 * k], ev[2 * k + 1]);
+        ksum += km;
+    }
+    *kernel_ms = ksum / nsteps;
+    for (auto& x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (e != hipSuccess) {
+        g_last_hip = (int)e;
+        return AF_ERR_HIP;
+    }
     return AF_OK;
 }
 
 const char* af_dominant_kernel(af_ctx* c) {
-    (void)c;
-    return "af_step (multi-kernel)";
+    if (c && c->variant == 1) return "af_step multi-kernel sequence";
+    return "af::k_fused<32, 8, 512, 0>";
 }
 
 }  // extern "C"

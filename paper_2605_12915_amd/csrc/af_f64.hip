@@ -191,12 +191,14 @@ hipError_t launch_step_multi_f64(const StepArgs& a) {
     const double lam1 = a.dt / a.h, lam0 = 0.5 * lam1;
     hipLaunchKernelGGL(k_centre, grd, blk, 0, a.stream, in, C, a.nx, a.ny, a.gamma, a.status);
     hipLaunchKernelGGL(k_incr, grd, blk, 0, a.stream, in, C, inc, a.nx, a.ny, a.gamma, lam0, lam1, a.status);
+    if (a.ev_begin) (void)hipEventRecord(a.ev_begin, a.stream);
     if (a.scheme == 0)
         hipLaunchKernelGGL(k_points<0>, grd, blk, 0, a.stream, in, C, inc, half, out, a.nx, a.ny, a.gamma, lam0, lam1,
                            a.status);
     else
         hipLaunchKernelGGL(k_points<1>, grd, blk, 0, a.stream, in, C, inc, half, out, a.nx, a.ny, a.gamma, lam0, lam1,
                            a.status);
+    if (a.ev_end) (void)hipEventRecord(a.ev_end, a.stream);
     hipLaunchKernelGGL(k_update, grd, blk, 0, a.stream, in, half, out, a.nx, a.ny, a.gamma, lam1);
     return hipGetLastError();
 }

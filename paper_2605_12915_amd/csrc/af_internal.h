@@ -25,6 +25,9 @@ struct StepArgs {
 };
 
 hipError_t launch_step_multi_f64(const StepArgs& a);
+hipError_t launch_step_fused_f64(const StepArgs& a);
+hipError_t prepare_fused_f64();
+size_t fused_lds_bytes();
 size_t scratch_bytes_multi_f64(int nx, int ny);
 
 hipError_t launch_diag_f64(const void* const s[16], int nx, int ny, double h, double gamma, double* partials,

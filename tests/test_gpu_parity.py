@@ -145,3 +145,27 @@ def test_config2_full_size_one_step(torch_dev, orc):
     err = _err(got, want)
     print("config2 per-plane error", err.max(), flush=True)
     assert err.max() <= TOL
+
+
+def test_multi_kernel_variant(torch_dev, orc, monkeypatch):
+    """The unfused four-kernel path (AF_VARIANT=multi) against the oracle too."""
+    monkeypatch.setenv("AF_VARIANT", "multi")
+    P = I.random_smooth(40, 24, seed=12, amp=0.1, vel=(0.3, -0.3))
+    s0 = P.state()
+    dt = P.dt_for_cfl(0.4)
+    want = orc.run(s0, P.h, P.gamma, dt, 4)
+    got, st = _run_gpu(torch_dev, P, s0, dt, 4)
+    assert "multi" in st.dominant_kernel()
+    assert _err(got, want).max() <= TOL
+
+
+def test_timing_api(torch_dev):
+    torch, dev = torch_dev
+    from paper_2605_12915_amd.stepper import Stepper
+    P = I.random_smooth(64, 64, seed=1, amp=0.05)
+    s0 = P.state()
+    st = Stepper(P.nx, P.ny, P.h, P.gamma, device=dev)
+    x = torch.from_numpy(s0).to(dev)
+    tot, ker = st.time_steps(x, P.dt_for_cfl(0.4), 4)
+    assert tot > 0 and 0 < ker <= tot
+    assert np.array_equal(x.cpu().numpy(), s0)
