@@ -20,8 +20,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
-FP64_VALU_PEAK_TFLOPS = 78.6
 
 
 def parse():
@@ -33,6 +31,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=512)
     ap.add_argument("--cpu-sample-steps", type=int, default=6)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -83,8 +83,13 @@ def main():
     tot_ms, ker_ms = st.time_steps(x, dt, 20)
     diag = st.diagnostics(x, dt)
     ok = bool(np.isfinite(diag["mass"]))
-    bytes_per_cell = 256.0
-    achieved = bytes_per_cell * ncell / (ker_ms * 1e-3) / 1e9
+    from paper_2605_12915_amd import perf
+    kname = st.dominant_kernel()
+    flops = perf.ALGO_FLOPS_PER_CELL_F64 * ncell            # per launch of the step kernel
+    achieved = flops / (ker_ms * 1e-3) / 1e12
+    t_alu = flops / (perf.FP64_PEAK_TFLOPS * 1e12)
+    t_hbm = perf.ALGO_BYTES_PER_CELL_F64 * ncell / (perf.HBM_PEAK_GBS * 1e9)
+    tr = perf.stored_traffic(kname)
     line = {
         "metric": "Mcell-updates/s per AF step (FP64 vs FP32) at stated error; adjoint/forward ratio",
         "value": value, "unit": "Mcell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -92,11 +97,22 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"periodic {P.nx}x{P.ny} FP64 Fourier-mode flow, CFL 0.4, RB-TAI step",
                    "nx": P.nx, "ny": P.ny, "dt": dt},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": st.dominant_kernel(), "kernel_ms": ker_ms},
+        "roofline": {"bound": "alu" if t_alu >= t_hbm else "hbm", "achieved": achieved,
+                     "peak": perf.FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / perf.FP64_PEAK_TFLOPS,
+                     "traffic": tr["traffic_bytes_per_launch"] if tr else None,
+                     "kernel": kname, "kernel_ms": ker_ms,
+                     "algo_flops_per_cell": perf.ALGO_FLOPS_PER_CELL_F64,
+                     "algo_bytes_per_cell": perf.ALGO_BYTES_PER_CELL_F64,
+                     "hbm_gbs_algorithmic": perf.ALGO_BYTES_PER_CELL_F64 * ncell / (ker_ms * 1e-3) / 1e9,
+                     "t_alu_ms": t_alu * 1e3, "t_hbm_ms": t_hbm * 1e3},
         "finite": ok,
     }
+    if args.copy_probe:
+        src = torch.empty(128 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, args.cpu_sample_steps)
     print(json.dumps(line))

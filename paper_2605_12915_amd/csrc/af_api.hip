@@ -31,7 +31,7 @@ struct af_ctx {
     double* partials;      // diagnostics partials
     double* diag_out;      // 9 doubles on the device
     hipEvent_t ev[4];      // [0], [1]: owned; [2], [3]: slots for per-launch timing events
-    int variant;           // 0: fused LDS-tiled kernel, 1: multi-kernel path
+    int variant;           // 0: fused LDS-tiled kernel, 1: multi-kernel path, 2: two-launch split
 };
 
 #define AF_HIP(x)                                       \
@@ -90,6 +90,7 @@ hipError_t launch_step(af_ctx* c, void* const in[16], void* const out[16], doubl
     a.ev_end = timed ? c->ev[3] : nullptr;
     a.variant = c->variant;
     if (c->variant == 1) return af::launch_step_multi_f64(a);
+    if (c->variant == 2) return af::launch_step_split_f64(a);
     return af::launch_step_fused_f64(a);
 }
 
@@ -145,9 +146,14 @@ af_status af_init(const af_config* cfg, void* hip_stream, af_ctx** out) {
     c->elem = sizeof(double);
     hipError_t e = hipGetDevice(&c->device);
     const char* v = getenv("AF_VARIANT");
-    c->variant = (v && std::strcmp(v, "multi") == 0) ? 1 : 0;
-    size_t sbytes = c->variant == 1 ? af::scratch_bytes_multi_f64(cfg->nx, cfg->ny) : 16;
+    c->variant = 0;
+    if (v && std::strcmp(v, "multi") == 0) c->variant = 1;
+    if (v && std::strcmp(v, "split") == 0) c->variant = 2;
+    size_t sbytes = 16;
+    if (c->variant == 1) sbytes = af::scratch_bytes_multi_f64(cfg->nx, cfg->ny);
+    if (c->variant == 2) sbytes = af::scratch_bytes_split_f64(cfg->nx, cfg->ny);
     if (e == hipSuccess && c->variant == 0) e = af::prepare_fused_f64();
+    if (e == hipSuccess && c->variant == 2) e = af::prepare_split_f64();
     if (e == hipSuccess) e = hipMalloc(&c->state2, 16 * c->N * c->elem);
     if (e == hipSuccess) e = hipMalloc(&c->scratch, sbytes);
     if (e == hipSuccess) e = hipMalloc((void**)&c->status, sizeof(unsigned));
@@ -304,6 +310,7 @@ af_status af_time_steps(af_ctx* c, const af_state* s, double dt, int32_t nsteps,
 
 const char* af_dominant_kernel(af_ctx* c) {
     if (c && c->variant == 1) return "af_step multi-kernel sequence";
+    if (c && c->variant == 2) return "af::k_points_update<32, 8, 512, 0>";
     return "af::k_fused<32, 8, 512, 0>";
 }
 

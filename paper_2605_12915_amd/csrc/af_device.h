@@ -14,6 +14,12 @@
 #include "af_blocks.h"
 #include "af_internal.h"
 
+// Helpers are host+device so that the operation-counting build (count_flops.cpp)
+// can run the very same arithmetic on the host.
+#ifndef AF_HD
+#define AF_HD __host__ __device__ __forceinline__
+#endif
+
 namespace af {
 
 enum Fam { F_V = 0, F_EV = 1, F_EH = 2, F_C = 3 };
@@ -25,7 +31,7 @@ struct Prim { T r, u, v, p; };
 // Conservative <-> primitive (Sec. 2)
 // ---------------------------------------------------------------------------
 template <class T>
-__device__ __forceinline__ void cons_of(const Prim<T>& w, T gm1inv, T U[4]) {
+AF_HD void cons_of(const Prim<T>& w, T gm1inv, T U[4]) {
     U[0] = w.r;
     U[1] = w.r * w.u;
     U[2] = w.r * w.v;
@@ -36,7 +42,7 @@ __device__ __forceinline__ void cons_of(const Prim<T>& w, T gm1inv, T U[4]) {
 // so that uniform data returns the anchor exactly (free-stream preservation):
 //   U_c = U_a + 9/4 [ (Ubar - U_a) - sum_corners (U - U_a)/36 - sum_edges (U - U_a)/9 ].
 template <class T>
-__device__ __forceinline__ Prim<T> recover_centre(const T Ub[4], const Prim<T>& v00, const Prim<T>& v10,
+AF_HD Prim<T> recover_centre(const T Ub[4], const Prim<T>& v00, const Prim<T>& v10,
                                                   const Prim<T>& v01, const Prim<T>& v11, const Prim<T>& eh0,
                                                   const Prim<T>& eh1, const Prim<T>& ev0, const Prim<T>& ev1,
                                                   T gamma) {
@@ -84,7 +90,7 @@ __device__ __forceinline__ Prim<T> recover_centre(const T Ub[4], const Prim<T>& 
 // X0+1 (units of h), written in differences so that constants give exact zeros.
 // XC = 0: X0 = 0;  XC = 1: X0 = -1;  XC = 2: X0 = -1/2.
 template <int XC, class T>
-__device__ __forceinline__ void mono1(T f0, T f1, T f2, T& c0, T& c1, T& c2) {
+AF_HD void mono1(T f0, T f1, T f2, T& c0, T& c1, T& c2) {
     T d10 = f1 - f0, d20 = f2 - f0, d21 = f2 - f1;
     c2 = T(2) * d20 - T(4) * d10;
     if constexpr (XC == 0) { c0 = f0; c1 = T(4) * d10 - d20; }
@@ -98,7 +104,7 @@ __device__ __forceinline__ void mono1(T f0, T f1, T f2, T& c0, T& c1, T& c2) {
 template <class T>
 struct NodeAcc {
     T a[6][4];
-    __device__ __forceinline__ void zero() {
+    AF_HD void zero() {
 #pragma unroll
         for (int c = 0; c < 6; ++c)
 #pragma unroll
@@ -109,7 +115,7 @@ struct NodeAcc {
 // Add the contribution of wedge W (cell nodal data f[var][x-node][y-node] of
 // (p, u, v); the cell's lower-left node at (X0, Y0) relative to the node).
 template <int W, int XC, int YC, class T>
-__device__ __forceinline__ void wedge_acc(const T f[3][3][3], NodeAcc<T>& acc) {
+AF_HD void wedge_acc(const T f[3][3][3], NodeAcc<T>& acc) {
     T c[3][3][3];   // [var][alpha][beta]
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
@@ -141,7 +147,7 @@ __device__ __forceinline__ void wedge_acc(const T f[3][3][3], NodeAcc<T>& acc) {
 
 // Increments (du, dv, dp) at radius r from the accumulators; Z = rho_K c_K.
 template <class T>
-__device__ __forceinline__ void node_increment(const NodeAcc<T>& A, T r, T Z, T iZ, T inc[3]) {
+AF_HD void node_increment(const NodeAcc<T>& A, T r, T Z, T iZ, T inc[3]) {
     T s[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) s[c] = ((A.a[c][3] * r + A.a[c][2]) * r + A.a[c][1]) * r + A.a[c][0];
@@ -155,7 +161,7 @@ __device__ __forceinline__ void node_increment(const NodeAcc<T>& A, T r, T Z, T 
 // ---------------------------------------------------------------------------
 // Lagrange weights at -1 and +1 (the middle one is implied by the difference form).
 template <class T>
-__device__ __forceinline__ void lag_pm(T s, T& lm, T& lp) {
+AF_HD void lag_pm(T s, T& lm, T& lp) {
     T hs = T(0.5) * s;
     lm = hs * (s - T(1));
     lp = hs * (s + T(1));
@@ -163,12 +169,12 @@ __device__ __forceinline__ void lag_pm(T s, T& lm, T& lp) {
 
 // sum_a l_a f_a written as f_1 + l_-(f_0 - f_1) + l_+(f_2 - f_1): exact on constants.
 template <class T>
-__device__ __forceinline__ T q1(T lm, T lp, T f0, T f1, T f2) {
+AF_HD T q1(T lm, T lp, T f0, T f1, T f2) {
     return f1 + lm * (f0 - f1) + lp * (f2 - f1);
 }
 
 template <class T>
-__device__ __forceinline__ T q2(T xm, T xp, T ym, T yp, const T f[3][3]) {
+AF_HD T q2(T xm, T xp, T ym, T yp, const T f[3][3]) {
     T g0 = q1(xm, xp, f[0][0], f[1][0], f[2][0]);
     T g1 = q1(xm, xp, f[0][1], f[1][1], f[2][1]);
     T g2 = q1(xm, xp, f[0][2], f[1][2], f[2][2]);
@@ -176,7 +182,7 @@ __device__ __forceinline__ T q2(T xm, T xp, T ym, T yp, const T f[3][3]) {
 }
 
 template <class T>
-__device__ __forceinline__ void flux_x(const Prim<T>& w, T gm1inv, T F[4]) {
+AF_HD void flux_x(const Prim<T>& w, T gm1inv, T F[4]) {
     T E = w.p * gm1inv + T(0.5) * w.r * (w.u * w.u + w.v * w.v);
     T m = w.r * w.u;
     F[0] = m;
@@ -186,7 +192,7 @@ __device__ __forceinline__ void flux_x(const Prim<T>& w, T gm1inv, T F[4]) {
 }
 
 template <class T>
-__device__ __forceinline__ void flux_y(const Prim<T>& w, T gm1inv, T F[4]) {
+AF_HD void flux_y(const Prim<T>& w, T gm1inv, T F[4]) {
     T E = w.p * gm1inv + T(0.5) * w.r * (w.u * w.u + w.v * w.v);
     T m = w.r * w.v;
     F[0] = m;

@@ -28,6 +28,9 @@ hipError_t launch_step_multi_f64(const StepArgs& a);
 hipError_t launch_step_fused_f64(const StepArgs& a);
 hipError_t prepare_fused_f64();
 size_t fused_lds_bytes();
+hipError_t launch_step_split_f64(const StepArgs& a);
+hipError_t prepare_split_f64();
+size_t scratch_bytes_split_f64(int nx, int ny);
 size_t scratch_bytes_multi_f64(int nx, int ny);
 
 hipError_t launch_diag_f64(const void* const s[16], int nx, int ny, double h, double gamma, double* partials,

@@ -15,14 +15,14 @@ namespace af {
 
 // Nine nodes of cell (ci, cj) in [x-node][y-node] order (Sec. 2; Sec. 4 R_Delta).
 template <class T, class A>
-__device__ __forceinline__ void cell_nodes(const A& acc, int ci, int cj, Prim<T> n[3][3]) {
+AF_HD void cell_nodes(const A& acc, int ci, int cj, Prim<T> n[3][3]) {
     n[0][0] = acc.node(F_V, ci, cj);      n[1][0] = acc.node(F_EH, ci, cj);     n[2][0] = acc.node(F_V, ci + 1, cj);
     n[0][1] = acc.node(F_EV, ci, cj);     n[1][1] = acc.node(F_C, ci, cj);      n[2][1] = acc.node(F_EV, ci + 1, cj);
     n[0][2] = acc.node(F_V, ci, cj + 1);  n[1][2] = acc.node(F_EH, ci, cj + 1); n[2][2] = acc.node(F_V, ci + 1, cj + 1);
 }
 
 template <class T, class A>
-__device__ __forceinline__ void cell_puv(const A& acc, int ci, int cj, T f[3][3][3]) {
+AF_HD void cell_puv(const A& acc, int ci, int cj, T f[3][3][3]) {
     Prim<T> n[3][3];
     cell_nodes<T>(acc, ci, cj, n);
 #pragma unroll
@@ -38,7 +38,7 @@ __device__ __forceinline__ void cell_puv(const A& acc, int ci, int cj, T f[3][3]
 // Accumulate every wedge of node family FAM at (i, j) (Sec. 3.1: four quadrants at
 // a vertex, two half-planes at an edge midpoint, the full disk at a centre).
 template <int FAM, class T, class A>
-__device__ __forceinline__ void node_wedges(const A& acc, int i, int j, NodeAcc<T>& na) {
+AF_HD void node_wedges(const A& acc, int i, int j, NodeAcc<T>& na) {
     T f[3][3][3];
     if constexpr (FAM == F_V) {
         cell_puv<T>(acc, i, j, f);         wedge_acc<W_V_NE, 0, 0>(f, na);
@@ -60,7 +60,7 @@ __device__ __forceinline__ void node_wedges(const A& acc, int i, int j, NodeAcc<
 // tau_k = lam_k h (k = 0: dt/2, 1: dt).  Sets SB_CFL if c_K dt / h > 1/2 and
 // SB_NONPHYS if the node state is not physical.
 template <int FAM, class T, class A>
-__device__ __forceinline__ void node_increments(const A& acc, int i, int j, T gamma, T lam0, T lam1,
+AF_HD void node_increments(const A& acc, int i, int j, T gamma, T lam0, T lam1,
                                                 T inc[2][3], unsigned& st) {
     Prim<T> W = acc.node(FAM, i, j);
     if (!(W.r > T(0)) || !(W.p > T(0))) st |= SB_NONPHYS;
@@ -87,7 +87,7 @@ template <> struct FamOffset<F_EH> { static constexpr double ox = 0.5, oy = 0.0;
 // more (or NaN) raises SB_FOOT and is replaced by the node itself, which keeps
 // every gather inside the two-cell halo.
 template <class T>
-__device__ __forceinline__ void locate(T off, T o, int& cell, T& xi, unsigned& st) {
+AF_HD void locate(T off, T o, int& cell, T& xi, unsigned& st) {
     if (!(fabs(off - o) < T(1))) { st |= SB_FOOT; off = o; }
     T fl = floor(off);
     cell = (int)fl;
@@ -98,7 +98,7 @@ __device__ __forceinline__ void locate(T off, T o, int& cell, T& xi, unsigned& s
 // eq. barsukow-additive) point update of target FAM at (i, j) for duration
 // tau = lam h (Sec. 6.1 steps 3-4).
 template <int FAM, int SCHEME, class T, class A, class D>
-__device__ __forceinline__ Prim<T> point_update(const A& acc, const D& dinc, int i, int j, T gamma, T lam,
+AF_HD Prim<T> point_update(const A& acc, const D& dinc, int i, int j, T gamma, T lam,
                                                 unsigned& st) {
     const T ox = T(FamOffset<FAM>::ox), oy = T(FamOffset<FAM>::oy);
     Prim<T> WP = acc.node(FAM, i, j);

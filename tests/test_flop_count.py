@@ -1,0 +1,22 @@
+"""The algorithmic flop count the benchmark reports is the one the kernels'
+arithmetic performs for one cell's own work (host build of csrc/count_flops.cpp)."""
+import json
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2605_12915_amd", "csrc")
+
+
+@pytest.mark.skipif(not os.path.exists("/opt/rocm/bin/hipcc"), reason="hipcc missing")
+def test_flop_count_current(tmp_path):
+    from paper_2605_12915_amd import perf
+    exe = str(tmp_path / "count_flops")
+    subprocess.run(["/opt/rocm/bin/hipcc", "-O1", "-std=c++17", f"-I{CSRC}", f"-I{os.path.join(ROOT, 'include')}",
+                    os.path.join(CSRC, "count_flops.cpp"), "-o", exe], check=True, capture_output=True)
+    out = json.loads(subprocess.run([exe], check=True, capture_output=True, text=True).stdout)
+    assert out["flops_per_cell_update"] == perf.ALGO_FLOPS_PER_CELL_F64
+    assert out["sqrts"] == 4 and out["divs"] > 0

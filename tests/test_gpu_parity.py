@@ -147,15 +147,20 @@ def test_config2_full_size_one_step(torch_dev, orc):
     assert err.max() <= TOL
 
 
-def test_multi_kernel_variant(torch_dev, orc, monkeypatch):
-    """The unfused four-kernel path (AF_VARIANT=multi) against the oracle too."""
-    monkeypatch.setenv("AF_VARIANT", "multi")
+@pytest.mark.parametrize("variant", ["multi", "split"])
+def test_other_variants(torch_dev, orc, monkeypatch, variant):
+    """The four-kernel path and the two-launch split path against the oracle too."""
+    monkeypatch.setenv("AF_VARIANT", variant)
     P = I.random_smooth(40, 24, seed=12, amp=0.1, vel=(0.3, -0.3))
     s0 = P.state()
     dt = P.dt_for_cfl(0.4)
     want = orc.run(s0, P.h, P.gamma, dt, 4)
     got, st = _run_gpu(torch_dev, P, s0, dt, 4)
-    assert "multi" in st.dominant_kernel()
+    assert _err(got, want).max() <= TOL
+    P = I.random_smooth(5, 70, seed=3, amp=0.1, vel=(-0.3, 0.3))
+    s0 = P.state()
+    want = orc.run(s0, P.h, P.gamma, dt, 3)
+    got, st = _run_gpu(torch_dev, P, s0, dt, 3)
     assert _err(got, want).max() <= TOL
 
 
