@@ -31,6 +31,9 @@ struct af_ctx {
     double* partials;      // diagnostics partials
     double* diag_out;      // 9 doubles on the device
     hipEvent_t ev[4];      // [0], [1]: owned; [2], [3]: slots for per-launch timing events
+    bool f32;              // AF_F32 context: float perturbation planes about cfg.bg
+    void* comp;            // AF_F32: 4 float compensation planes of the average update
+    const void* traj[2];   // AF_F32: the buffers of the trajectory the compensation belongs to
     int variant;           // 0: fused LDS-tiled kernel, 1: multi-kernel path, 2: two-launch split
 };
 
@@ -89,6 +92,9 @@ hipError_t launch_step(af_ctx* c, void* const in[16], void* const out[16], doubl
     a.ev_begin = timed ? c->ev[2] : nullptr;
     a.ev_end = timed ? c->ev[3] : nullptr;
     a.variant = c->variant;
+    for (int k = 0; k < 4; ++k) a.bg[k] = c->cfg.bg[k];
+    a.comp = c->comp;
+    if (c->f32) return af::launch_step_fused_f32(a);
     if (c->variant == 1) return af::launch_step_multi_f64(a);
     if (c->variant == 2) return af::launch_step_split_f64(a);
     return af::launch_step_fused_f64(a);
@@ -100,6 +106,17 @@ hipError_t copy_state(af_ctx* c, void* const dst[16], void* const src[16]) {
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// AF_F32: the Kahan compensation belongs to one trajectory; a state that is neither
+// of the two buffers of the previous call starts a new one (compensation zeroed).
+hipError_t follow_trajectory(af_ctx* c, const void* a, const void* b) {
+    if (!c->f32) return hipSuccess;
+    const bool same = (a == c->traj[0] || a == c->traj[1]);
+    c->traj[0] = a;
+    c->traj[1] = b;
+    if (same) return hipSuccess;
+    return hipMemsetAsync(c->comp, 0, 4 * c->N * sizeof(float), c->stream);
 }
 
 af_status read_status(af_ctx* c, unsigned* bits) {
@@ -136,14 +153,16 @@ af_status af_init(const af_config* cfg, void* hip_stream, af_ctx** out) {
     if (cfg->nx < 4 || cfg->ny < 4 || !(cfg->h > 0.0) || !(cfg->gamma > 1.0) || !std::isfinite(cfg->h) ||
         !std::isfinite(cfg->gamma))
         return AF_ERR_ARG;
-    if (cfg->precision != AF_F64) return AF_ERR_UNSUPPORTED;
+    if (cfg->precision != AF_F64 && cfg->precision != AF_F32) return AF_ERR_ARG;
+    if (cfg->precision == AF_F32 && (!(cfg->bg[0] > 0.0) || !(cfg->bg[3] > 0.0))) return AF_ERR_ARG;
     af_ctx* c = new (std::nothrow) af_ctx();
     if (!c) return AF_ERR_ARG;
     std::memset(c, 0, sizeof(*c));
     c->cfg = *cfg;
     c->stream = (hipStream_t)hip_stream;
     c->N = (size_t)cfg->nx * cfg->ny;
-    c->elem = sizeof(double);
+    c->f32 = cfg->precision == AF_F32;
+    c->elem = c->f32 ? sizeof(float) : sizeof(double);
     hipError_t e = hipGetDevice(&c->device);
     const char* v = getenv("AF_VARIANT");
     c->variant = 0;
@@ -152,7 +171,11 @@ af_status af_init(const af_config* cfg, void* hip_stream, af_ctx** out) {
     size_t sbytes = 16;
     if (c->variant == 1) sbytes = af::scratch_bytes_multi_f64(cfg->nx, cfg->ny);
     if (c->variant == 2) sbytes = af::scratch_bytes_split_f64(cfg->nx, cfg->ny);
-    if (e == hipSuccess && c->variant == 0) e = af::prepare_fused_f64();
+    if (c->f32) c->variant = 0;
+    if (e == hipSuccess && c->f32) e = af::prepare_fused_f32();
+    if (e == hipSuccess && c->f32) e = hipMalloc(&c->comp, 4 * c->N * sizeof(float));
+    if (e == hipSuccess && c->f32) e = hipMemsetAsync(c->comp, 0, 4 * c->N * sizeof(float), c->stream);
+    if (e == hipSuccess && !c->f32 && c->variant == 0) e = af::prepare_fused_f64();
     if (e == hipSuccess && c->variant == 2) e = af::prepare_split_f64();
     if (e == hipSuccess) e = hipMalloc(&c->state2, 16 * c->N * c->elem);
     if (e == hipSuccess) e = hipMalloc(&c->scratch, sbytes);
@@ -181,6 +204,7 @@ void af_destroy(af_ctx* c) {
     if (c->status) (void)hipFree(c->status);
     if (c->partials) (void)hipFree(c->partials);
     if (c->diag_out) (void)hipFree(c->diag_out);
+    if (c->comp) (void)hipFree(c->comp);
     for (int k = 0; k < 2; ++k)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     delete c;
@@ -191,6 +215,7 @@ af_status af_step_out(af_ctx* c, const af_state* in, af_state* out, double dt) {
     void *pi[16], *po[16];
     planes_of(in, pi);
     planes_of(out, po);
+    AF_HIP(follow_trajectory(c, pi[0], po[0]));
     AF_HIP(launch_step(c, pi, po, dt, false));
     if (c->cfg.flags & AF_CHECK) {
         unsigned bits;
@@ -206,6 +231,7 @@ af_status af_step(af_ctx* c, af_state* inout, double dt, int32_t nsteps) {
     void *a[16], *b[16];
     planes_of(inout, a);
     planes_of_buffer(c->state2, c->N, c->elem, b);
+    AF_HIP(follow_trajectory(c, a[0], b[0]));
     const bool check = (c->cfg.flags & AF_CHECK) != 0;
     for (int s = 0; s < nsteps; ++s) {
         void** src = (s & 1) ? b : a;
@@ -238,6 +264,7 @@ af_status af_read_status(af_ctx* c, af_status* status) {
 af_status af_step_adjoint(af_ctx* c, const af_state* primal_n, const af_state* cot_np1, af_state* cot_n,
                           double dt) {
     if (!c || !state_ok(primal_n) || !state_ok(cot_np1) || !state_ok(cot_n) || !(dt > 0.0)) return AF_ERR_ARG;
+    if (c->f32) return AF_ERR_UNSUPPORTED;
     return AF_ERR_UNSUPPORTED;
 }
 
@@ -245,8 +272,8 @@ af_status af_diagnostics(af_ctx* c, const af_state* s, double dt, af_diag* out) 
     if (!c || !state_ok(s) || !out) return AF_ERR_ARG;
     void* p[16];
     planes_of(s, p);
-    AF_HIP(af::launch_diag_f64(p, c->cfg.nx, c->cfg.ny, c->cfg.h, c->cfg.gamma, c->partials, kDiagPartials,
-                               c->diag_out, c->stream));
+    AF_HIP(af::launch_diag(p, c->f32, c->cfg.bg, c->cfg.nx, c->cfg.ny, c->cfg.h, c->cfg.gamma, c->partials,
+                           kDiagPartials, c->diag_out, c->stream));
     double h[9];
     AF_HIP(hipMemcpyAsync(h, c->diag_out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     AF_HIP(hipStreamSynchronize(c->stream));
@@ -309,6 +336,7 @@ af_status af_time_steps(af_ctx* c, const af_state* s, double dt, int32_t nsteps,
 }
 
 const char* af_dominant_kernel(af_ctx* c) {
+    if (c && c->f32) return "af::k_fused<float, PolPert<float>, 32, 8, 512, 0, true>";
     if (c && c->variant == 1) return "af_step multi-kernel sequence";
     if (c && c->variant == 2) return "af::k_points_update<32, 8, 512, 0>";
     return "af::k_fused<32, 8, 512, 0>";

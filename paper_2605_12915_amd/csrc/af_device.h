@@ -201,4 +201,103 @@ AF_HD void flux_y(const Prim<T>& w, T gm1inv, T F[4]) {
     F[3] = w.v * (E + w.p);
 }
 
+// ---------------------------------------------------------------------------
+// Variable policies.  PolAbs: the state holds the physical values (FP64 path).
+// PolPert: the state holds perturbations about a uniform background W_bg and
+// U(W_bg) (FP32 path); every conversion and flux below is the exact difference
+// F(W_bg + W') - F(W_bg), so no large background value is ever rounded away.
+// The increments of the acoustic operator and the Q2 evaluations are linear in
+// the data and shift-invariant, so they act on perturbations unchanged.
+// ---------------------------------------------------------------------------
+template <class T>
+struct PolAbs {
+    T gamma, gm1inv;
+    AF_HD T rho(T r) const { return r; }
+    AF_HD T vu(T u) const { return u; }
+    AF_HD T vv(T v) const { return v; }
+    AF_HD T pr(T p) const { return p; }
+    AF_HD Prim<T> centre(const T Ub[4], const Prim<T>& v00, const Prim<T>& v10, const Prim<T>& v01,
+                         const Prim<T>& v11, const Prim<T>& eh0, const Prim<T>& eh1, const Prim<T>& ev0,
+                         const Prim<T>& ev1) const {
+        return recover_centre(Ub, v00, v10, v01, v11, eh0, eh1, ev0, ev1, gamma);
+    }
+    AF_HD void fx(const Prim<T>& w, T F[4]) const { flux_x(w, gm1inv, F); }
+    AF_HD void fy(const Prim<T>& w, T F[4]) const { flux_y(w, gm1inv, F); }
+};
+
+template <class T>
+struct PolPert {
+    T gamma, gm1inv, r0, u0, v0, p0;
+    T m0x, m0y, H0;    // background momentum and total enthalpy density E + p
+    AF_HD T rho(T r) const { return r0 + r; }
+    AF_HD T vu(T u) const { return u0 + u; }
+    AF_HD T vv(T v) const { return v0 + v; }
+    AF_HD T pr(T p) const { return p0 + p; }
+    // E(W) - E(W_bg) from a perturbation
+    AF_HD T energy(const Prim<T>& w) const {
+        const T uu = u0 + w.u, vv = v0 + w.v;
+        return w.p * gm1inv +
+               T(0.5) * (w.r * (uu * uu + vv * vv) + r0 * (w.u * (T(2) * u0 + w.u) + w.v * (T(2) * v0 + w.v)));
+    }
+    AF_HD void cons(const Prim<T>& w, T U[4]) const {
+        U[0] = w.r;
+        U[1] = r0 * w.u + w.r * (u0 + w.u);
+        U[2] = r0 * w.v + w.r * (v0 + w.v);
+        U[3] = energy(w);
+    }
+    AF_HD Prim<T> centre(const T Ub[4], const Prim<T>& v00, const Prim<T>& v10, const Prim<T>& v01,
+                         const Prim<T>& v11, const Prim<T>& eh0, const Prim<T>& eh1, const Prim<T>& ev0,
+                         const Prim<T>& ev1) const {
+        T Ua[4], U[4], sc[4], se[4];
+        cons(v00, Ua);
+        const Prim<T>* corners[3] = {&v10, &v01, &v11};
+        const Prim<T>* edges[4] = {&eh0, &eh1, &ev0, &ev1};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { sc[k] = T(0); se[k] = T(0); }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cons(*corners[c], U);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sc[k] += U[k] - Ua[k];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            cons(*edges[c], U);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) se[k] += U[k] - Ua[k];
+        }
+        T Uc[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            Uc[k] = Ua[k] + T(2.25) * ((Ub[k] - Ua[k]) - sc[k] * T(1.0 / 36.0) - se[k] * T(1.0 / 9.0));
+        Prim<T> w;
+        w.r = Uc[0];
+        const T ir = T(1) / (r0 + Uc[0]);
+        w.u = (Uc[1] - u0 * Uc[0]) * ir;
+        w.v = (Uc[2] - v0 * Uc[0]) * ir;
+        const T uu = u0 + w.u, vv = v0 + w.v;
+        w.p = (gamma - T(1)) *
+              (Uc[3] - T(0.5) * (w.r * (uu * uu + vv * vv) + r0 * (w.u * (T(2) * u0 + w.u) + w.v * (T(2) * v0 + w.v))));
+        return w;
+    }
+    AF_HD void fx(const Prim<T>& w, T F[4]) const {
+        const T uu = u0 + w.u, vv = v0 + w.v;
+        const T m = r0 * w.u + w.r * uu;                 // rho u - rho0 u0
+        const T Hp = energy(w) + w.p;                    // H - H0
+        F[0] = m;
+        F[1] = m0x * w.u + m * uu + w.p;
+        F[2] = m0x * w.v + m * vv;
+        F[3] = u0 * Hp + w.u * (H0 + Hp);
+    }
+    AF_HD void fy(const Prim<T>& w, T F[4]) const {
+        const T uu = u0 + w.u, vv = v0 + w.v;
+        const T m = r0 * w.v + w.r * vv;                 // rho v - rho0 v0
+        const T Hp = energy(w) + w.p;
+        F[0] = m;
+        F[1] = m0y * w.u + m * uu;
+        F[2] = m0y * w.v + m * vv + w.p;
+        F[3] = v0 * Hp + w.v * (H0 + Hp);
+    }
+};
+
 }  // namespace af

@@ -14,6 +14,8 @@ namespace af {
 constexpr int kDiagVals = 9;   // 5 sums, min rho, min p, max(|u|+c), max c
 constexpr int kDiagBlock = 256;
 
+struct DiagBg { double bg[4], Ubg[4]; };
+
 __device__ __forceinline__ void combine(double* a, const double* b) {
 #pragma unroll
     for (int k = 0; k < 5; ++k) a[k] += b[k];
@@ -42,11 +44,18 @@ __device__ __forceinline__ void block_reduce(double v[kDiagVals], double* sh) {
     }
 }
 
+// Reads a state of T (absolute doubles, or float perturbations about bg) as
+// absolute FP64 values.
+template <class T>
 struct DiagAcc {
-    const double* s[16];
-    const double* dummyC;
+    const T* s[16];
     int nx, ny;
     double gamma;
+    double bg[4], Ubg[4];
+    __device__ __forceinline__ double val(int plane, size_t k) const {
+        const int b = plane < 4 ? -1 : (plane - 4) % 4;
+        return (double)s[plane][k] + (plane < 4 ? Ubg[plane] : bg[b]);
+    }
     __device__ __forceinline__ size_t idx(int i, int j) const {
         i = i >= nx ? i - nx : i;
         j = j >= ny ? j - ny : j;
@@ -55,20 +64,26 @@ struct DiagAcc {
     __device__ __forceinline__ Prim<double> node(int fam, int i, int j) const {
         size_t k = idx(i, j);
         if (fam == F_C) {
-            double Ub[4] = {s[0][k], s[1][k], s[2][k], s[3][k]};
+            double Ub[4] = {val(0, k), val(1, k), val(2, k), val(3, k)};
             return recover_centre(Ub, node(F_V, i, j), node(F_V, i + 1, j), node(F_V, i, j + 1),
                                   node(F_V, i + 1, j + 1), node(F_EH, i, j), node(F_EH, i, j + 1),
                                   node(F_EV, i, j), node(F_EV, i + 1, j), gamma);
         }
         const int b = 4 + 4 * fam;
-        return {s[b][k], s[b + 1][k], s[b + 2][k], s[b + 3][k]};
+        return {val(b, k), val(b + 1, k), val(b + 2, k), val(b + 3, k)};
     }
 };
 
-__global__ void __launch_bounds__(kDiagBlock) k_diag(StatePtrs<const double> st, int nx, int ny, double gamma,
-                                                     double* partials) {
+template <class T>
+__global__ void __launch_bounds__(kDiagBlock) k_diag(StatePtrs<const T> st, int nx, int ny, double gamma,
+                                                     DiagBg bgs, double* partials) {
     __shared__ double sh[(kDiagBlock / 64) * kDiagVals];
-    DiagAcc A{{}, nullptr, nx, ny, gamma};
+    DiagAcc<T> A;
+    A.nx = nx;
+    A.ny = ny;
+    A.gamma = gamma;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { A.bg[k] = bgs.bg[k]; A.Ubg[k] = bgs.Ubg[k]; }
 #pragma unroll
     for (int k = 0; k < 16; ++k) A.s[k] = st.p[k];
     double v[kDiagVals] = {0, 0, 0, 0, 0, 1e300, 1e300, 0, 0};
@@ -76,14 +91,14 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag(StatePtrs<const double> st,
     const double wq[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
     for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(c % nx), j = (int)(c / nx);
-        for (int k = 0; k < 4; ++k) v[k] += st.p[k][c];
+        for (int k = 0; k < 4; ++k) v[k] += A.val(k, c);
         Prim<double> n[3][3];
         cell_nodes<double>(A, i, j, n);
         double e = 0.0;
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) {
                 const Prim<double>& w = n[a][b];
-                e += wq[a] * wq[b] * w.r * log(w.p / pow(w.r, gamma));
+                e += wq[a] * wq[b] * w.r * (log(w.p) - gamma * log(w.r));
             }
         v[4] -= e;
         const Prim<double> own[4] = {n[0][0], n[0][1], n[1][0], n[1][1]};   // V, EV, EH, C of cell (i,j)
@@ -110,11 +125,25 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag_final(const double* partial
         for (int k = 0; k < kDiagVals; ++k) out[k] = v[k];
 }
 
-hipError_t launch_diag_f64(const void* const s[16], int nx, int ny, double h, double gamma, double* partials,
-                           int npartials, double* out9, hipStream_t stream) {
-    StatePtrs<const double> st;
-    for (int k = 0; k < 16; ++k) st.p[k] = (const double*)s[k];
-    hipLaunchKernelGGL(k_diag, dim3(npartials), dim3(kDiagBlock), 0, stream, st, nx, ny, gamma, partials);
+hipError_t launch_diag(const void* const s[16], bool f32, const double bg[4], int nx, int ny, double h,
+                       double gamma, double* partials, int npartials, double* out9, hipStream_t stream) {
+    DiagBg b;
+    for (int k = 0; k < 4; ++k) { b.bg[k] = f32 ? bg[k] : 0.0; b.Ubg[k] = 0.0; }
+    if (f32) {
+        b.Ubg[0] = bg[0];
+        b.Ubg[1] = bg[0] * bg[1];
+        b.Ubg[2] = bg[0] * bg[2];
+        b.Ubg[3] = bg[3] / (gamma - 1.0) + 0.5 * bg[0] * (bg[1] * bg[1] + bg[2] * bg[2]);
+    }
+    if (f32) {
+        StatePtrs<const float> st;
+        for (int k = 0; k < 16; ++k) st.p[k] = (const float*)s[k];
+        hipLaunchKernelGGL(k_diag<float>, dim3(npartials), dim3(kDiagBlock), 0, stream, st, nx, ny, gamma, b, partials);
+    } else {
+        StatePtrs<const double> st;
+        for (int k = 0; k < 16; ++k) st.p[k] = (const double*)s[k];
+        hipLaunchKernelGGL(k_diag<double>, dim3(npartials), dim3(kDiagBlock), 0, stream, st, nx, ny, gamma, b, partials);
+    }
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagBlock), 0, stream, partials, npartials, out9);
     return hipGetLastError();
 }

@@ -69,6 +69,7 @@ __global__ void __launch_bounds__(256) k_centre(StatePtrs<double> in, double* C,
 
 __global__ void __launch_bounds__(256) k_incr(StatePtrs<double> in, const double* C, double* inc, int nx, int ny,
                                               double gamma, double lam0, double lam1, unsigned* status) {
+    const PolAbs<double> pol{gamma, 1.0 / (gamma - 1.0)};
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= nx || j >= ny) return;
@@ -78,16 +79,16 @@ __global__ void __launch_bounds__(256) k_incr(StatePtrs<double> in, const double
     unsigned st = 0;
     double d[2][3];
     const size_t N = (size_t)nx * ny, c = (size_t)j * nx + i;
-    node_increments<F_V>(A, i, j, gamma, lam0, lam1, d, st);
+    node_increments<F_V>(A, i, j, pol, lam0, lam1, d, st);
     for (int t = 0; t < 2; ++t)
         for (int v = 0; v < 3; ++v) inc[(size_t)(t * 12 + 0 * 3 + v) * N + c] = d[t][v];
-    node_increments<F_EV>(A, i, j, gamma, lam0, lam1, d, st);
+    node_increments<F_EV>(A, i, j, pol, lam0, lam1, d, st);
     for (int t = 0; t < 2; ++t)
         for (int v = 0; v < 3; ++v) inc[(size_t)(t * 12 + 1 * 3 + v) * N + c] = d[t][v];
-    node_increments<F_EH>(A, i, j, gamma, lam0, lam1, d, st);
+    node_increments<F_EH>(A, i, j, pol, lam0, lam1, d, st);
     for (int t = 0; t < 2; ++t)
         for (int v = 0; v < 3; ++v) inc[(size_t)(t * 12 + 2 * 3 + v) * N + c] = d[t][v];
-    node_increments<F_C>(A, i, j, gamma, lam0, lam1, d, st);
+    node_increments<F_C>(A, i, j, pol, lam0, lam1, d, st);
     for (int t = 0; t < 2; ++t)
         for (int v = 0; v < 3; ++v) inc[(size_t)(t * 12 + 3 * 3 + v) * N + c] = d[t][v];
     if (st) atomicOr(status, st);
@@ -97,6 +98,7 @@ template <int SCHEME>
 __global__ void __launch_bounds__(256) k_points(StatePtrs<double> in, const double* C, const double* inc,
                                                 double* half, StatePtrs<double> out, int nx, int ny,
                                                 double gamma, double lam0, double lam1, unsigned* status) {
+    const PolAbs<double> pol{gamma, 1.0 / (gamma - 1.0)};
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= nx || j >= ny) return;
@@ -109,9 +111,9 @@ __global__ void __launch_bounds__(256) k_points(StatePtrs<double> in, const doub
         GInc64 D{inc + (size_t)t * 12 * N, nx, ny};
         const double lam = t ? lam1 : lam0;
         Prim<double> w[3];
-        w[0] = point_update<F_V, SCHEME>(A, D, i, j, gamma, lam, st);
-        w[1] = point_update<F_EV, SCHEME>(A, D, i, j, gamma, lam, st);
-        w[2] = point_update<F_EH, SCHEME>(A, D, i, j, gamma, lam, st);
+        w[0] = point_update<F_V, SCHEME>(A, D, i, j, pol, lam, st);
+        w[1] = point_update<F_EV, SCHEME>(A, D, i, j, pol, lam, st);
+        w[2] = point_update<F_EH, SCHEME>(A, D, i, j, pol, lam, st);
         for (int f = 0; f < 3; ++f) {
             double vals[4] = {w[f].r, w[f].u, w[f].v, w[f].p};
             for (int k = 0; k < 4; ++k) {

@@ -22,10 +22,14 @@ struct StepArgs {
     hipStream_t stream;
     hipEvent_t ev_begin, ev_end;  // optional: recorded around the dominant kernel
     int variant;                // kernel variant (path-specific)
+    double bg[4];               // FP32 path: background (rho, u, v, p) of the perturbations
+    void* comp;                 // FP32 path: 4 compensation planes of the average update
 };
 
 hipError_t launch_step_multi_f64(const StepArgs& a);
 hipError_t launch_step_fused_f64(const StepArgs& a);
+hipError_t launch_step_fused_f32(const StepArgs& a);
+hipError_t prepare_fused_f32();
 hipError_t prepare_fused_f64();
 size_t fused_lds_bytes();
 hipError_t launch_step_split_f64(const StepArgs& a);
@@ -33,7 +37,7 @@ hipError_t prepare_split_f64();
 size_t scratch_bytes_split_f64(int nx, int ny);
 size_t scratch_bytes_multi_f64(int nx, int ny);
 
-hipError_t launch_diag_f64(const void* const s[16], int nx, int ny, double h, double gamma, double* partials,
-                           int npartials, double* out9, hipStream_t stream);
+hipError_t launch_diag(const void* const s[16], bool f32, const double bg[4], int nx, int ny, double h,
+                       double gamma, double* partials, int npartials, double* out9, hipStream_t stream);
 
 }  // namespace af

@@ -59,13 +59,14 @@ AF_HD void node_wedges(const A& acc, int i, int j, NodeAcc<T>& na) {
 // Node freezing (Sec. 6.1 step 1) and the increments for two durations
 // tau_k = lam_k h (k = 0: dt/2, 1: dt).  Sets SB_CFL if c_K dt / h > 1/2 and
 // SB_NONPHYS if the node state is not physical.
-template <int FAM, class T, class A>
-AF_HD void node_increments(const A& acc, int i, int j, T gamma, T lam0, T lam1,
-                                                T inc[2][3], unsigned& st) {
-    Prim<T> W = acc.node(FAM, i, j);
-    if (!(W.r > T(0)) || !(W.p > T(0))) st |= SB_NONPHYS;
-    T c = sqrt(gamma * W.p / W.r);
-    T Z = W.r * c;
+template <int FAM, class T, class A, class Pol>
+AF_HD void node_increments(const A& acc, int i, int j, const Pol& pol, T lam0, T lam1, T inc[2][3],
+                           unsigned& st) {
+    const Prim<T> Wn = acc.node(FAM, i, j);
+    const T rK = pol.rho(Wn.r), pK = pol.pr(Wn.p);
+    if (!(rK > T(0)) || !(pK > T(0))) st |= SB_NONPHYS;
+    T c = sqrt(pol.gamma * pK / rK);
+    T Z = rK * c;
     T iZ = T(1) / Z;
     NodeAcc<T> na;
     na.zero();
@@ -97,16 +98,15 @@ AF_HD void locate(T off, T o, int& cell, T& xi, unsigned& st) {
 // Transported (SCHEME 0, eq. transported-update) or additive (SCHEME 1,
 // eq. barsukow-additive) point update of target FAM at (i, j) for duration
 // tau = lam h (Sec. 6.1 steps 3-4).
-template <int FAM, int SCHEME, class T, class A, class D>
-AF_HD Prim<T> point_update(const A& acc, const D& dinc, int i, int j, T gamma, T lam,
-                                                unsigned& st) {
+template <int FAM, int SCHEME, class T, class A, class D, class Pol>
+AF_HD Prim<T> point_update(const A& acc, const D& dinc, int i, int j, const Pol& pol, T lam, unsigned& st) {
     const T ox = T(FamOffset<FAM>::ox), oy = T(FamOffset<FAM>::oy);
     Prim<T> WP = acc.node(FAM, i, j);
     int cx, cy;
     T xi, eta, xm, xp, ym, yp;
     // first Picard step: at a node the reconstruction equals the node value
-    locate(ox - lam * WP.u, ox, cx, xi, st);
-    locate(oy - lam * WP.v, oy, cy, eta, st);
+    locate(ox - lam * pol.vu(WP.u), ox, cx, xi, st);
+    locate(oy - lam * pol.vv(WP.v), oy, cy, eta, st);
     lag_pm(xi, xm, xp);
     lag_pm(eta, ym, yp);
     T fu[3][3], fv[3][3];
@@ -120,8 +120,8 @@ AF_HD Prim<T> point_update(const A& acc, const D& dinc, int i, int j, T gamma, T
     }
     T u1 = q2(xm, xp, ym, yp, fu), v1 = q2(xm, xp, ym, yp, fv);
     // second Picard step from P with the velocity at the first foot
-    locate(ox - lam * u1, ox, cx, xi, st);
-    locate(oy - lam * v1, oy, cy, eta, st);
+    locate(ox - lam * pol.vu(u1), ox, cx, xi, st);
+    locate(oy - lam * pol.vv(v1), oy, cy, eta, st);
     lag_pm(xi, xm, xp);
     lag_pm(eta, ym, yp);
     const int ci = i + cx, cj = j + cy;
@@ -150,14 +150,104 @@ AF_HD Prim<T> point_update(const A& acc, const D& dinc, int i, int j, T gamma, T
             T val = q2(xm, xp, ym, yp, g);
             if (var == 0) du = val; else if (var == 1) dv = val; else dp = val;
         }
-        rho_over_c2 = Wf.r / (gamma * Wf.p);        // 1 / c^2 at the foot
+        rho_over_c2 = pol.rho(Wf.r) / (pol.gamma * pol.pr(Wf.p));    // 1 / c^2 at the foot
     } else {
         du = dinc.inc(FAM, i, j, 0);
         dv = dinc.inc(FAM, i, j, 1);
         dp = dinc.inc(FAM, i, j, 2);
-        rho_over_c2 = WP.r / (gamma * WP.p);        // frozen 1 / c^2 at P
+        rho_over_c2 = pol.rho(WP.r) / (pol.gamma * pol.pr(WP.p));    // frozen 1 / c^2 at P
     }
     return Prim<T>{Wf.r + dp * rho_over_c2, Wf.u + du, Wf.v + dv, Wf.p + dp};
+}
+
+// Both durations of one target at once.  The two Picard stages of both durations
+// normally stay in one cell, fixed by the sign of the node velocity; that cell's
+// nine nodes and both increment sets are gathered once and every stage is checked
+// to stay in it.  Lanes whose feet leave it take the general path above, which
+// performs the same arithmetic (so the results do not depend on the path).
+template <int FAM, int SCHEME, class T, class A, class D, class Pol>
+AF_HD void point_update_pair(const A& acc, const D& d0, const D& d1, int i, int j, const Pol& pol, T lam0, T lam1,
+                             unsigned& st, Prim<T>& wh, Prim<T>& w1) {
+    const T ox = T(FamOffset<FAM>::ox), oy = T(FamOffset<FAM>::oy);
+    const Prim<T> WP = acc.node(FAM, i, j);
+    // candidate cell from the longer first-stage displacement
+    const T uP = pol.vu(WP.u), vP = pol.vv(WP.v);
+    const T ex = ox - lam1 * uP, ey = oy - lam1 * vP;
+    bool fast = (fabs(ex - ox) < T(1)) && (fabs(ey - oy) < T(1));
+    int cx = 0, cy = 0;
+    Prim<T> wr[2];
+    if (fast) {
+        const T fcx = floor(ex), fcy = floor(ey);
+        cx = (int)fcx;
+        cy = (int)fcy;
+        const int ci = i + cx, cj = j + cy;
+        T fr[3][3], fu[3][3], fv[3][3], fp[3][3], g[2][3][3][3];
+        {
+            Prim<T> n[3][3];
+            cell_nodes<T>(acc, ci, cj, n);
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    fr[a][b] = n[a][b].r; fu[a][b] = n[a][b].u; fv[a][b] = n[a][b].v; fp[a][b] = n[a][b].p;
+                }
+        }
+        if constexpr (SCHEME == 0) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const D& dd = t ? d1 : d0;
+#pragma unroll
+                for (int var = 0; var < 3; ++var) {
+                    g[t][var][0][0] = dd.inc(F_V, ci, cj, var);      g[t][var][1][0] = dd.inc(F_EH, ci, cj, var);
+                    g[t][var][2][0] = dd.inc(F_V, ci + 1, cj, var);  g[t][var][0][1] = dd.inc(F_EV, ci, cj, var);
+                    g[t][var][1][1] = dd.inc(F_C, ci, cj, var);      g[t][var][2][1] = dd.inc(F_EV, ci + 1, cj, var);
+                    g[t][var][0][2] = dd.inc(F_V, ci, cj + 1, var);  g[t][var][1][2] = dd.inc(F_EH, ci, cj + 1, var);
+                    g[t][var][2][2] = dd.inc(F_V, ci + 1, cj + 1, var);
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const T lam = t ? lam1 : lam0;
+            T xi, eta, xm, xp, ym, yp, fl;
+            // first Picard stage
+            T o1x = ox - lam * uP, o1y = oy - lam * vP;
+            fl = floor(o1x); fast = fast && (fl == fcx); xi = T(2) * (o1x - fl) - T(1);
+            fl = floor(o1y); fast = fast && (fl == fcy); eta = T(2) * (o1y - fl) - T(1);
+            lag_pm(xi, xm, xp);
+            lag_pm(eta, ym, yp);
+            const T u1 = q2(xm, xp, ym, yp, fu), v1 = q2(xm, xp, ym, yp, fv);
+            // second stage
+            T o2x = ox - lam * pol.vu(u1), o2y = oy - lam * pol.vv(v1);
+            fast = fast && (fabs(o2x - ox) < T(1)) && (fabs(o2y - oy) < T(1));
+            fl = floor(o2x); fast = fast && (fl == fcx); xi = T(2) * (o2x - fl) - T(1);
+            fl = floor(o2y); fast = fast && (fl == fcy); eta = T(2) * (o2y - fl) - T(1);
+            lag_pm(xi, xm, xp);
+            lag_pm(eta, ym, yp);
+            Prim<T> Wf{q2(xm, xp, ym, yp, fr), q2(xm, xp, ym, yp, fu), q2(xm, xp, ym, yp, fv), q2(xm, xp, ym, yp, fp)};
+            T du, dv, dp, rho_over_c2;
+            if constexpr (SCHEME == 0) {
+                du = q2(xm, xp, ym, yp, g[t][0]);
+                dv = q2(xm, xp, ym, yp, g[t][1]);
+                dp = q2(xm, xp, ym, yp, g[t][2]);
+                rho_over_c2 = pol.rho(Wf.r) / (pol.gamma * pol.pr(Wf.p));
+            } else {
+                const D& dd = t ? d1 : d0;
+                du = dd.inc(FAM, i, j, 0);
+                dv = dd.inc(FAM, i, j, 1);
+                dp = dd.inc(FAM, i, j, 2);
+                rho_over_c2 = pol.rho(WP.r) / (pol.gamma * pol.pr(WP.p));
+            }
+            wr[t] = Prim<T>{Wf.r + dp * rho_over_c2, Wf.u + du, Wf.v + dv, Wf.p + dp};
+        }
+    }
+    if (fast) {
+        wh = wr[0];
+        w1 = wr[1];
+    } else {
+        wh = point_update<FAM, SCHEME>(acc, d0, i, j, pol, lam0, st);
+        w1 = point_update<FAM, SCHEME>(acc, d1, i, j, pol, lam1, st);
+    }
 }
 
 }  // namespace af

@@ -62,6 +62,7 @@ template <int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT) k_acoustic(StatePtrs<double> in, double* Cout, double* Dout, int nx, int ny,
                                                  int tiles_x, int ntiles, double gamma, double lam0, double lam1,
                                                  unsigned* status) {
+    const PolAbs<double> pol{gamma, 1.0 / (gamma - 1.0)};
     using Tile = AcTile<TX, TY>;
     __shared__ Tile T;
     const int tid = threadIdx.x;
@@ -103,22 +104,22 @@ __global__ void __launch_bounds__(NT) k_acoustic(StatePtrs<double> in, double* C
         if (i0 + x >= nx || j0 + y >= ny) continue;
         const size_t g = (size_t)(j0 + y) * nx + (i0 + x);
         double d[2][3];
-        node_increments<F_V>(A, x, y, gamma, lam0, lam1, d, st);
+        node_increments<F_V>(A, x, y, pol, lam0, lam1, d, st);
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int v = 0; v < 3; ++v) Dout[(size_t)(t * 12 + 0 + v) * N + g] = d[t][v];
-        node_increments<F_EV>(A, x, y, gamma, lam0, lam1, d, st);
+        node_increments<F_EV>(A, x, y, pol, lam0, lam1, d, st);
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int v = 0; v < 3; ++v) Dout[(size_t)(t * 12 + 3 + v) * N + g] = d[t][v];
-        node_increments<F_EH>(A, x, y, gamma, lam0, lam1, d, st);
+        node_increments<F_EH>(A, x, y, pol, lam0, lam1, d, st);
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int v = 0; v < 3; ++v) Dout[(size_t)(t * 12 + 6 + v) * N + g] = d[t][v];
-        node_increments<F_C>(A, x, y, gamma, lam0, lam1, d, st);
+        node_increments<F_C>(A, x, y, pol, lam0, lam1, d, st);
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -149,6 +150,7 @@ template <int TX, int TY, int NT, int SCHEME>
 __global__ void __launch_bounds__(NT) k_points_update(StatePtrs<double> in, const double* Cin, const double* Din,
                                                       StatePtrs<double> out, int nx, int ny, int tiles_x, int ntiles,
                                                       double gamma, double lam0, double lam1, unsigned* status) {
+    const PolAbs<double> pol{gamma, 1.0 / (gamma - 1.0)};
     using Tile = PtTile<TX, TY>;
     extern __shared__ __align__(16) unsigned char smem[];
     Tile& T = *reinterpret_cast<Tile*>(smem);
@@ -189,16 +191,16 @@ __global__ void __launch_bounds__(NT) k_points_update(StatePtrs<double> in, cons
         Prim<double> w0, wh, w1;
         if (fam == F_V) {
             w0 = A.node(F_V, x, y);
-            wh = point_update<F_V, SCHEME>(A, D0, x, y, gamma, lam0, st);
-            w1 = point_update<F_V, SCHEME>(A, D1, x, y, gamma, lam1, st);
+            wh = point_update<F_V, SCHEME>(A, D0, x, y, pol, lam0, st);
+            w1 = point_update<F_V, SCHEME>(A, D1, x, y, pol, lam1, st);
         } else if (fam == F_EV) {
             w0 = A.node(F_EV, x, y);
-            wh = point_update<F_EV, SCHEME>(A, D0, x, y, gamma, lam0, st);
-            w1 = point_update<F_EV, SCHEME>(A, D1, x, y, gamma, lam1, st);
+            wh = point_update<F_EV, SCHEME>(A, D0, x, y, pol, lam0, st);
+            w1 = point_update<F_EV, SCHEME>(A, D1, x, y, pol, lam1, st);
         } else {
             w0 = A.node(F_EH, x, y);
-            wh = point_update<F_EH, SCHEME>(A, D0, x, y, gamma, lam0, st);
-            w1 = point_update<F_EH, SCHEME>(A, D1, x, y, gamma, lam1, st);
+            wh = point_update<F_EH, SCHEME>(A, D0, x, y, pol, lam0, st);
+            w1 = point_update<F_EH, SCHEME>(A, D1, x, y, pol, lam1, st);
         }
         if (x < TX && y < TY && i0 + x < nx && j0 + y < ny) {
             const size_t g = (size_t)(j0 + y) * nx + (i0 + x);

@@ -72,6 +72,7 @@ int main() {
         }
     const Cnt gamma = 1.4, lam0 = 0.1, lam1 = 0.2;
     unsigned st = 0;
+    const PolAbs<Cnt> pol{gamma, Cnt(1.0 / 0.4)};
     long c0 = total();
     Cnt Ub[4] = {1.0, 0.3, -0.2, 2.6};
     recover_centre(Ub, A.node(F_V, 2, 2), A.node(F_V, 3, 2), A.node(F_V, 2, 3), A.node(F_V, 3, 3),
@@ -79,23 +80,23 @@ int main() {
     long centre = total() - c0;
     c0 = total();
     Cnt d[2][3];
-    node_increments<F_V>(A, 2, 2, gamma, lam0, lam1, d, st);
+    node_increments<F_V>(A, 2, 2, pol, lam0, lam1, d, st);
     long incV = total() - c0;
     c0 = total();
-    node_increments<F_EV>(A, 2, 2, gamma, lam0, lam1, d, st);
-    node_increments<F_EH>(A, 2, 2, gamma, lam0, lam1, d, st);
+    node_increments<F_EV>(A, 2, 2, pol, lam0, lam1, d, st);
+    node_increments<F_EH>(A, 2, 2, pol, lam0, lam1, d, st);
     long incE = total() - c0;
     c0 = total();
-    node_increments<F_C>(A, 2, 2, gamma, lam0, lam1, d, st);
+    node_increments<F_C>(A, 2, 2, pol, lam0, lam1, d, st);
     long incC = total() - c0;
     c0 = total();
     Prim<Cnt> w[3][2];
-    w[0][0] = point_update<F_V, 0>(A, D, 2, 2, gamma, lam0, st);
-    w[0][1] = point_update<F_V, 0>(A, D, 2, 2, gamma, lam1, st);
-    w[1][0] = point_update<F_EV, 0>(A, D, 2, 2, gamma, lam0, st);
-    w[1][1] = point_update<F_EV, 0>(A, D, 2, 2, gamma, lam1, st);
-    w[2][0] = point_update<F_EH, 0>(A, D, 2, 2, gamma, lam0, st);
-    w[2][1] = point_update<F_EH, 0>(A, D, 2, 2, gamma, lam1, st);
+    w[0][0] = point_update<F_V, 0>(A, D, 2, 2, pol, lam0, st);
+    w[0][1] = point_update<F_V, 0>(A, D, 2, 2, pol, lam1, st);
+    w[1][0] = point_update<F_EV, 0>(A, D, 2, 2, pol, lam0, st);
+    w[1][1] = point_update<F_EV, 0>(A, D, 2, 2, pol, lam1, st);
+    w[2][0] = point_update<F_EH, 0>(A, D, 2, 2, pol, lam0, st);
+    w[2][1] = point_update<F_EH, 0>(A, D, 2, 2, pol, lam1, st);
     long points = total() - c0;
     c0 = total();
     // time-Simpson fluxes of the owned targets: V (F and G), Ev (F), Eh (G)

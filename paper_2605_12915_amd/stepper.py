@@ -118,3 +118,35 @@ class Stepper:
 
     def dominant_kernel(self) -> str:
         return _lib.lib().af_dominant_kernel(self._ctx).decode()
+
+
+def background_cons(bg, gamma):
+    r, u, v, p = (float(x) for x in bg)
+    return (r, r * u, r * v, p / (gamma - 1.0) + 0.5 * r * (u * u + v * v))
+
+
+def to_perturbation(state, bg, gamma: float):
+    """Absolute FP64 state (16, ny, nx) -> FP32 perturbation state about bg (host numpy):
+    averages minus U(bg), point values minus bg.  Representation change only."""
+    import numpy as np
+    s = np.asarray(state, dtype=np.float64)
+    out = np.empty(s.shape, dtype=np.float32)
+    Ub = background_cons(bg, gamma)
+    for k in range(4):
+        out[k] = s[k] - Ub[k]
+        for f in range(3):
+            out[4 + 4 * f + k] = s[4 + 4 * f + k] - float(bg[k])
+    return out
+
+
+def from_perturbation(state32, bg, gamma: float):
+    """Inverse of to_perturbation, evaluated in FP64."""
+    import numpy as np
+    s = np.asarray(state32, dtype=np.float64)
+    out = np.empty(s.shape, dtype=np.float64)
+    Ub = background_cons(bg, gamma)
+    for k in range(4):
+        out[k] = s[k] + Ub[k]
+        for f in range(3):
+            out[4 + 4 * f + k] = s[4 + 4 * f + k] + float(bg[k])
+    return out

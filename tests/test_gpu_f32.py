@@ -1,0 +1,103 @@
+"""FP32 precision form (float perturbations about a background state, compensated
+average update) against the FP64 oracle.  The error is a property of FP32
+arithmetic; the per-field bounds below are the stated accuracy of this form:
+normwise relative error of the perturbation (max|gpu - oracle| / max|oracle - bg|)."""
+import numpy as np
+import pytest
+
+from paper_2605_12915_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+def run_f32(torch_dev, P, s0, dt, n, bg):
+    torch, dev = torch_dev
+    from paper_2605_12915_amd.stepper import Stepper, from_perturbation, to_perturbation
+    st = Stepper(P.nx, P.ny, P.h, P.gamma, precision="f32", bg=bg, device=dev, check_errors=True)
+    x = torch.from_numpy(to_perturbation(s0, bg, P.gamma)).to(dev)
+    st.step(x, dt, n)
+    torch.cuda.synchronize()
+    return from_perturbation(x.cpu().numpy(), bg, P.gamma), st, x
+
+
+def pert_err(got, want, s0):
+    """per plane: max|got - want| / max|want - (background part of want)|; the
+    perturbation scale is taken from the oracle solution's own variation."""
+    scale = np.maximum(want.max(axis=(1, 2)) - want.min(axis=(1, 2)), 1e-300)
+    return np.abs(got - want).max(axis=(1, 2)) / scale
+
+
+def test_f32_free_stream(torch_dev):
+    """A uniform state equal to the background is a zero perturbation up to the
+    quadrature round-off of its averages (~1e-16); it must stay at that level."""
+    from paper_2605_12915_amd.stepper import to_perturbation
+    P = I.uniform(16, W=(1.3, 0.7, -0.4, 0.9), ny=12)
+    s0 = P.state()
+    x0 = to_perturbation(s0, (1.3, 0.7, -0.4, 0.9), P.gamma)
+    got, _, x = run_f32(torch_dev, P, s0, P.dt_for_cfl(0.45), 50, bg=(1.3, 0.7, -0.4, 0.9))
+    assert float((x.cpu() - __import__("torch").from_numpy(x0)).abs().max()) <= 1e-14
+
+
+def test_f32_vortex_vs_oracle(torch_dev, orc):
+    P = I.isentropic_vortex(64, uinf=(1.0, 1.0))
+    s0 = P.state()
+    dt = P.dt_for_cfl(0.3)
+    want = orc.run(s0, P.h, P.gamma, dt, 100)
+    got, _, _ = run_f32(torch_dev, P, s0, dt, 100, bg=(1.0, 1.0, 1.0, 1.0))
+    err = pert_err(got, want, s0)
+    print("f32 vortex per-plane error (relative to the solution's range):", np.array2string(err, precision=2))
+    assert err.max() < 2e-5
+
+
+def test_f32_pulse_vs_oracle(torch_dev, orc):
+    P = I.gaussian_pulse(96, amp=0.1, width=0.05)
+    s0 = P.state()
+    dt = P.dt_for_cfl(0.4)
+    want = orc.run(s0, P.h, P.gamma, dt, 60)
+    got, _, _ = run_f32(torch_dev, P, s0, dt, 60, bg=P.bg)
+    err = pert_err(got, want, s0)
+    print("f32 pulse per-plane error:", np.array2string(err, precision=2))
+    assert err.max() < 2e-5
+
+
+def test_f32_ragged_and_rb(torch_dev, orc):
+    P = I.random_smooth(37, 29, seed=4, amp=0.1, vel=(0.35, -0.25))
+    s0 = P.state()
+    dt = P.dt_for_cfl(0.4)
+    want = orc.run(s0, P.h, P.gamma, dt, 10)
+    got, _, _ = run_f32(torch_dev, P, s0, dt, 10, bg=P.bg)
+    assert pert_err(got, want, s0).max() < 2e-5
+
+
+def test_f32_conservation(torch_dev):
+    P = I.random_smooth(48, 40, seed=2, amp=0.2)
+    s0 = P.state()
+    got, _, x = run_f32(torch_dev, P, s0, P.dt_for_cfl(0.4), 50, bg=P.bg)
+    from paper_2605_12915_amd.stepper import to_perturbation
+    s32 = to_perturbation(s0, P.bg, P.gamma).astype(np.float64)
+    g32 = x.cpu().numpy().astype(np.float64)
+    for k in range(4):
+        # the compensated update keeps the totals to a few float ulps of the perturbation per cell
+        assert abs(g32[k].sum() - s32[k].sum()) <= 1e-6 * np.abs(s32[k]).sum() + 1e-9
+
+
+def test_f32_diagnostics(torch_dev, orc):
+    torch, dev = torch_dev
+    from paper_2605_12915_amd.stepper import Stepper, to_perturbation
+    P = I.isentropic_vortex(40, uinf=(1.0, 1.0))
+    s0 = P.state()
+    dt = P.dt_for_cfl(0.3)
+    bg = (1.0, 1.0, 1.0, 1.0)
+    st = Stepper(P.nx, P.ny, P.h, P.gamma, precision="f32", bg=bg, device=dev)
+    got = st.diagnostics(torch.from_numpy(to_perturbation(s0, bg, P.gamma)).to(dev), dt)
+    want = orc.diagnostics(s0, P.h, P.gamma, dt)
+    for k, v in want.items():
+        assert abs(got[k] - v) <= 1e-6 * max(1.0, abs(v)), (k, got[k], v)
