@@ -1,0 +1,559 @@
+// Reverse-mode derivative of one FP64 RB-TAI step (transposed Sec. 6.1 dataflow).
+//
+// cot_n = (d step / d state_n)^T cot_np1 at fixed dt.  The forward intermediates
+// (recovered centres W^C and the node increments of both durations) are recomputed
+// from state_n by the multi-kernel path's k_centre/k_incr; the reverse sweep then
+// runs in the opposite order of the forward dataflow, one thread per cell, with
+// FP64 atomics accumulating the scattered contributions:
+//   k_adj_points   average update and space-time Simpson fluxes (transposed), then
+//                  for every target and duration the transposed transported point
+//                  update: density closure, Q2 evaluation of W and of the increments
+//                  at the foot (values and foot position), the two Picard stages.
+//                  Scatters into cot_n (point planes), lambda_C and lambda_D.
+//   k_adj_incr     transposed node increments: Horner in r, freezing
+//                  (c_K = sqrt(gamma p / rho), Z = rho c), transposed monomial blocks
+//                  and Lagrange-to-monomial transforms of every wedge.
+//   k_adj_centre   transposed centre recovery (prim(U_c), inverse Simpson, U(W) at
+//                  the eight boundary nodes); writes the average planes of cot_n.
+// The floor() that locates a foot is piecewise constant: its derivative is zero
+// (the usual convention; the step is continuous across faces because R_h and I_h are).
+#include <hip/hip_runtime.h>
+
+#include "af_internal.h"
+#include "af_kernels.h"
+
+namespace af {
+
+struct AdjNodes {
+    const double* s[16];
+    const double* C;
+    int nx, ny;
+    __device__ __forceinline__ size_t idx(int i, int j) const {
+        i = (i < 0) ? i + nx : (i >= nx ? i - nx : i);
+        j = (j < 0) ? j + ny : (j >= ny ? j - ny : j);
+        return (size_t)j * nx + i;
+    }
+    __device__ __forceinline__ Prim<double> node(int fam, int i, int j) const {
+        const size_t k = idx(i, j);
+        if (fam == F_C) {
+            const size_t N = (size_t)nx * ny;
+            return {C[k], C[N + k], C[2 * N + k], C[3 * N + k]};
+        }
+        const int b = 4 + 4 * fam;
+        return {s[b][k], s[b + 1][k], s[b + 2][k], s[b + 3][k]};
+    }
+};
+
+struct AdjInc {
+    const double* d;    // 12 planes of one duration
+    int nx, ny;
+    __device__ __forceinline__ double inc(int fam, int i, int j, int var) const {
+        i = (i < 0) ? i + nx : (i >= nx ? i - nx : i);
+        j = (j < 0) ? j + ny : (j >= ny ? j - ny : j);
+        return d[(size_t)(fam * 3 + var) * nx * ny + (size_t)j * nx + i];
+    }
+};
+
+// Scatter targets of the reverse sweep.
+struct AdjOut {
+    double* S[16];      // cot_n
+    double* lC;         // 4 planes: adjoint of the recovered centres
+    double* lD;         // 24 planes: adjoint of the increments [tau][fam][var]
+    int nx, ny;
+    __device__ __forceinline__ size_t idx(int i, int j) const {
+        i = (i < 0) ? i + nx : (i >= nx ? i - nx : i);
+        j = (j < 0) ? j + ny : (j >= ny ? j - ny : j);
+        return (size_t)j * nx + i;
+    }
+    // add g = (d rho, d u, d v, d p) to node fam of cell (i, j)
+    __device__ __forceinline__ void node(int fam, int i, int j, const double g[4]) const {
+        const size_t k = idx(i, j);
+        if (fam == F_C) {
+            const size_t N = (size_t)nx * ny;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (g[q] != 0.0) atomicAdd(lC + q * N + k, g[q]);
+            return;
+        }
+        const int b = 4 + 4 * fam;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (g[q] != 0.0) atomicAdd(S[b + q] + k, g[q]);
+    }
+    __device__ __forceinline__ void inc(int t, int fam, int i, int j, const double g[3]) const {
+        const size_t k = idx(i, j), N = (size_t)nx * ny;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if (g[q] != 0.0) atomicAdd(lD + (size_t)(t * 12 + fam * 3 + q) * N + k, g[q]);
+    }
+};
+
+// Node (family, cell offset) of entry [a][b] of cell (ci, cj) (Sec. 2 layout).
+__device__ __forceinline__ void node_of(int a, int b, int ci, int cj, int& fam, int& i, int& j) {
+    const int fa[3][3] = {{F_V, F_EV, F_V}, {F_EH, F_C, F_EH}, {F_V, F_EV, F_V}};   // [a][b]
+    fam = fa[a][b];
+    i = ci + (a == 2 ? 1 : 0);
+    j = cj + (b == 2 ? 1 : 0);
+}
+
+__device__ __forceinline__ void lagr(double s, double l[3], double dl[3]) {
+    l[0] = 0.5 * s * (s - 1.0);
+    l[1] = 1.0 - s * s;
+    l[2] = 0.5 * s * (s + 1.0);
+    dl[0] = s - 0.5;
+    dl[1] = -2.0 * s;
+    dl[2] = s + 0.5;
+}
+
+// Flux Jacobians transposed: g += (dF/dW)^T nu, W = (rho, u, v, p).
+__device__ __forceinline__ void flux_x_T(const Prim<double>& w, double gamma, const double nu[4], double g[4]) {
+    const double q2 = 0.5 * (w.u * w.u + w.v * w.v);
+    const double E = w.p / (gamma - 1.0) + w.r * q2;
+    g[0] += nu[0] * w.u + nu[1] * w.u * w.u + nu[2] * w.u * w.v + nu[3] * w.u * q2;
+    g[1] += nu[0] * w.r + nu[1] * 2.0 * w.r * w.u + nu[2] * w.r * w.v + nu[3] * (E + w.p + w.r * w.u * w.u);
+    g[2] += nu[2] * w.r * w.u + nu[3] * w.r * w.u * w.v;
+    g[3] += nu[1] + nu[3] * w.u * gamma / (gamma - 1.0);
+}
+
+__device__ __forceinline__ void flux_y_T(const Prim<double>& w, double gamma, const double nu[4], double g[4]) {
+    const double q2 = 0.5 * (w.u * w.u + w.v * w.v);
+    const double E = w.p / (gamma - 1.0) + w.r * q2;
+    g[0] += nu[0] * w.v + nu[1] * w.u * w.v + nu[2] * w.v * w.v + nu[3] * w.v * q2;
+    g[1] += nu[1] * w.r * w.v + nu[3] * w.r * w.u * w.v;
+    g[2] += nu[0] * w.r + nu[1] * w.r * w.u + nu[2] * 2.0 * w.r * w.v + nu[3] * (E + w.p + w.r * w.v * w.v);
+    g[3] += nu[2] + nu[3] * w.v * gamma / (gamma - 1.0);
+}
+
+// Transposed transported point update (scheme 0) of target FAM at (i, j) for the
+// duration tau = lam h; lw = adjoint of the new point value.
+template <int FAM>
+__device__ void point_update_adj(const AdjNodes& A, const AdjInc& D, const AdjOut& O, int t, int i, int j,
+                                 double gamma, double lam, const double lw[4]) {
+    const double ox = FamOffset<FAM>::ox, oy = FamOffset<FAM>::oy;
+    const Prim<double> WP = A.node(FAM, i, j);
+    unsigned st = 0;
+    // ---- forward recomputation ----
+    int cx1, cy1, cx2, cy2;
+    double xi1, eta1, xi2, eta2;
+    locate(ox - lam * WP.u, ox, cx1, xi1, st);
+    locate(oy - lam * WP.v, oy, cy1, eta1, st);
+    double lx1[3], dlx1[3], ly1[3], dly1[3];
+    lagr(xi1, lx1, dlx1);
+    lagr(eta1, ly1, dly1);
+    Prim<double> n1[3][3];
+    cell_nodes<double>(A, i + cx1, j + cy1, n1);
+    double u1 = 0.0, v1 = 0.0, du1x = 0.0, du1y = 0.0, dv1x = 0.0, dv1y = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            u1 += lx1[a] * ly1[b] * n1[a][b].u;
+            v1 += lx1[a] * ly1[b] * n1[a][b].v;
+            du1x += dlx1[a] * ly1[b] * n1[a][b].u;
+            du1y += lx1[a] * dly1[b] * n1[a][b].u;
+            dv1x += dlx1[a] * ly1[b] * n1[a][b].v;
+            dv1y += lx1[a] * dly1[b] * n1[a][b].v;
+        }
+    locate(ox - lam * u1, ox, cx2, xi2, st);
+    locate(oy - lam * v1, oy, cy2, eta2, st);
+    double lx2[3], dlx2[3], ly2[3], dly2[3];
+    lagr(xi2, lx2, dlx2);
+    lagr(eta2, ly2, dly2);
+    const int ci = i + cx2, cj = j + cy2;
+    Prim<double> n2[3][3];
+    cell_nodes<double>(A, ci, cj, n2);
+    double Wf[4] = {0, 0, 0, 0}, dWx[4] = {0, 0, 0, 0}, dWy[4] = {0, 0, 0, 0};
+    double Df[3] = {0, 0, 0}, dDx[3] = {0, 0, 0}, dDy[3] = {0, 0, 0};
+    double dn[3][3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double w = lx2[a] * ly2[b], wx = dlx2[a] * ly2[b], wy = lx2[a] * dly2[b];
+            const double f[4] = {n2[a][b].r, n2[a][b].u, n2[a][b].v, n2[a][b].p};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { Wf[q] += w * f[q]; dWx[q] += wx * f[q]; dWy[q] += wy * f[q]; }
+            int fam, ii, jj;
+            node_of(a, b, ci, cj, fam, ii, jj);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                dn[a][b][q] = D.inc(fam, ii, jj, q);
+                Df[q] += w * dn[a][b][q];
+                dDx[q] += wx * dn[a][b][q];
+                dDy[q] += wy * dn[a][b][q];
+            }
+        }
+    // ---- reverse ----
+    // compose: rho = rho_f + dp rho_f / (gamma p_f), u = u_f + du, v = v_f + dv, p = p_f + dp
+    const double qinv = 1.0 / (gamma * Wf[3]);
+    double lWf[4], lDf[3];
+    lWf[0] = lw[0] * (1.0 + Df[2] * qinv);
+    lWf[1] = lw[1];
+    lWf[2] = lw[2];
+    lWf[3] = lw[3] - lw[0] * Df[2] * Wf[0] * qinv / Wf[3];
+    lDf[0] = lw[1];
+    lDf[1] = lw[2];
+    lDf[2] = lw[3] + lw[0] * Wf[0] * qinv;
+    // Q2 values at the foot -> nodes of the foot cell
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double w = lx2[a] * ly2[b];
+            int fam, ii, jj;
+            node_of(a, b, ci, cj, fam, ii, jj);
+            const double g[4] = {w * lWf[0], w * lWf[1], w * lWf[2], w * lWf[3]};
+            O.node(fam, ii, jj, g);
+            const double gd[3] = {w * lDf[0], w * lDf[1], w * lDf[2]};
+            O.inc(t, fam, ii, jj, gd);
+        }
+    // foot position: xi2 = 2 (off - floor(off)) - 1, off = ox - lam u1
+    double lxi2 = 0.0, leta2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) { lxi2 += lWf[q] * dWx[q]; leta2 += lWf[q] * dWy[q]; }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) { lxi2 += lDf[q] * dDx[q]; leta2 += lDf[q] * dDy[q]; }
+    const double lu1 = -2.0 * lam * lxi2, lv1 = -2.0 * lam * leta2;
+    // first stage: u1 = Q2(u) at (xi1, eta1)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double w = lx1[a] * ly1[b];
+            int fam, ii, jj;
+            node_of(a, b, i + cx1, j + cy1, fam, ii, jj);
+            const double g[4] = {0.0, w * lu1, w * lv1, 0.0};
+            O.node(fam, ii, jj, g);
+        }
+    const double lxi1 = lu1 * du1x + lv1 * dv1x, leta1 = lu1 * du1y + lv1 * dv1y;
+    const double gP[4] = {0.0, -2.0 * lam * lxi1, -2.0 * lam * leta1, 0.0};
+    O.node(FAM, i, j, gP);
+}
+
+struct PlaneList { double* p[40]; };
+
+__global__ void __launch_bounds__(256) k_adj_zero_list(PlaneList L, int nplanes, size_t N) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < N; k += stride)
+        for (int p = 0; p < nplanes; ++p) L.p[p][k] = 0.0;
+}
+
+__global__ void __launch_bounds__(256) k_adj_points(StatePtrs<double> prim, const double* C, const double* Dfwd,
+                                                    StatePtrs<double> cot1, AdjOut O, double gamma, double lam0,
+                                                    double lam1) {
+    const int nx = O.nx, ny = O.ny;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= nx || j >= ny) return;
+    AdjNodes A{{}, C, nx, ny};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) A.s[k] = prim.p[k];
+    const size_t N = (size_t)nx * ny;
+    AdjInc D0{Dfwd, nx, ny}, D1{Dfwd + 12 * N, nx, ny};
+    const PolAbs<double> pol{gamma, 1.0 / (gamma - 1.0)};
+    auto lU = [&](int a, int b, int k) -> double { return cot1.p[k][A.idx(a, b)]; };
+    // adjoints of the time-integrated edge fluxes touching this cell's nodes
+    double nuFV[4], nuGV[4], nuFE[4], nuGE[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double muF_ij = lam1 * (lU(i, j, k) - lU(i - 1, j, k));
+        const double muF_ijm = lam1 * (lU(i, j - 1, k) - lU(i - 1, j - 1, k));
+        const double muG_ij = lam1 * (lU(i, j, k) - lU(i, j - 1, k));
+        const double muG_imj = lam1 * (lU(i - 1, j, k) - lU(i - 1, j - 1, k));
+        nuFV[k] = (muF_ij + muF_ijm) * (1.0 / 6.0);
+        nuGV[k] = (muG_ij + muG_imj) * (1.0 / 6.0);
+        nuFE[k] = muF_ij * (4.0 / 6.0);
+        nuGE[k] = muG_ij * (4.0 / 6.0);
+    }
+    const double wsig[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+    const size_t c = A.idx(i, j);
+    unsigned st = 0;
+#pragma unroll
+    for (int fam = 0; fam < 3; ++fam) {
+        Prim<double> w[3];
+        w[0] = A.node(fam, i, j);
+        if (fam == F_V) {
+            w[1] = point_update<F_V, 0>(A, D0, i, j, pol, lam0, st);
+            w[2] = point_update<F_V, 0>(A, D1, i, j, pol, lam1, st);
+        } else if (fam == F_EV) {
+            w[1] = point_update<F_EV, 0>(A, D0, i, j, pol, lam0, st);
+            w[2] = point_update<F_EV, 0>(A, D1, i, j, pol, lam1, st);
+        } else {
+            w[1] = point_update<F_EH, 0>(A, D0, i, j, pol, lam0, st);
+            w[2] = point_update<F_EH, 0>(A, D1, i, j, pol, lam1, st);
+        }
+        double lw[3][4];
+#pragma unroll
+        for (int sg = 0; sg < 3; ++sg) {
+            double nu[4];
+            double g[4] = {0.0, 0.0, 0.0, 0.0};
+            if (fam == F_V) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) nu[k] = wsig[sg] * nuFV[k];
+                flux_x_T(w[sg], gamma, nu, g);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) nu[k] = wsig[sg] * nuGV[k];
+                flux_y_T(w[sg], gamma, nu, g);
+            } else if (fam == F_EV) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) nu[k] = wsig[sg] * nuFE[k];
+                flux_x_T(w[sg], gamma, nu, g);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) nu[k] = wsig[sg] * nuGE[k];
+                flux_y_T(w[sg], gamma, nu, g);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) lw[sg][k] = g[k];
+        }
+        // the new point value is also an output of the step
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lw[2][k] += cot1.p[4 + 4 * fam + k][c];
+        O.node(fam, i, j, lw[0]);
+        if (fam == F_V) {
+            point_update_adj<F_V>(A, D0, O, 0, i, j, gamma, lam0, lw[1]);
+            point_update_adj<F_V>(A, D1, O, 1, i, j, gamma, lam1, lw[2]);
+        } else if (fam == F_EV) {
+            point_update_adj<F_EV>(A, D0, O, 0, i, j, gamma, lam0, lw[1]);
+            point_update_adj<F_EV>(A, D1, O, 1, i, j, gamma, lam1, lw[2]);
+        } else {
+            point_update_adj<F_EH>(A, D0, O, 0, i, j, gamma, lam0, lw[1]);
+            point_update_adj<F_EH>(A, D1, O, 1, i, j, gamma, lam1, lw[2]);
+        }
+    }
+}
+
+// Transposed 1-D Lagrange-to-monomial transform (see mono1): (lc0, lc1, lc2) -> (lf0, lf1, lf2).
+template <int XC>
+__device__ __forceinline__ void mono1_T(double c0, double c1, double c2, double& f0, double& f1, double& f2) {
+    if constexpr (XC == 0) { f0 = c0 - 3.0 * c1 + 2.0 * c2; f1 = 4.0 * c1 - 4.0 * c2; f2 = -c1 + 2.0 * c2; }
+    else if constexpr (XC == 1) { f0 = c1 + 2.0 * c2; f1 = -4.0 * c1 - 4.0 * c2; f2 = c0 + 3.0 * c1 + 2.0 * c2; }
+    else { f0 = -c1 + 2.0 * c2; f1 = c0 - 4.0 * c2; f2 = c1 + 2.0 * c2; }
+}
+
+// Transposed wedge: adjoint of the accumulators -> adjoint of the cell's nodal (p, u, v),
+// scattered to the nodes of cell (ci, cj).
+template <int W, int XC, int YC>
+__device__ __forceinline__ void wedge_adj(const double la[6][4], const AdjOut& O, int ci, int cj) {
+    double lc[3][3][3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) lc[v][a][b] = 0.0;
+#pragma unroll
+    for (int al = 0; al < 3; ++al)
+#pragma unroll
+        for (int be = 0; be < 3; ++be) {
+            if (al + be == 0) continue;
+            const int m = al + be - 1;
+            const double* B = kBlk[W][al][be];
+            double sp = 0.0, su = 0.0, sv = 0.0;
+            if (B[0] != 0.0) sp += B[0] * la[0][m];
+            if (B[3] != 0.0) sp += B[3] * la[2][m];
+            if (B[6] != 0.0) sp += B[6] * la[4][m];
+            if (B[1] != 0.0) su += B[1] * la[1][m];
+            if (B[4] != 0.0) su += B[4] * la[3][m];
+            if (B[7] != 0.0) su += B[7] * la[5][m];
+            if (B[2] != 0.0) sv += B[2] * la[1][m];
+            if (B[5] != 0.0) sv += B[5] * la[3][m];
+            if (B[8] != 0.0) sv += B[8] * la[5][m];
+            lc[0][al][be] = sp;
+            lc[1][al][be] = su;
+            lc[2][al][be] = sv;
+        }
+    double lf[3][3][3];   // [var][x-node][y-node]
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        double lg[3][3];  // [alpha][y-node]
+#pragma unroll
+        for (int al = 0; al < 3; ++al) mono1_T<YC>(lc[v][al][0], lc[v][al][1], lc[v][al][2], lg[al][0], lg[al][1], lg[al][2]);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) mono1_T<XC>(lg[0][b], lg[1][b], lg[2][b], lf[v][0][b], lf[v][1][b], lf[v][2][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            int fam, ii, jj;
+            node_of(a, b, ci, cj, fam, ii, jj);
+            const double g[4] = {0.0, lf[1][a][b], lf[2][a][b], lf[0][a][b]};
+            O.node(fam, ii, jj, g);
+        }
+}
+
+template <int FAM>
+__device__ void incr_adj(const AdjNodes& A, const AdjOut& O, int i, int j, double gamma, double lam0, double lam1) {
+    const size_t N = (size_t)O.nx * O.ny, k = A.idx(i, j);
+    double li[2][3];
+    bool any = false;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            li[t][q] = O.lD[(size_t)(t * 12 + FAM * 3 + q) * N + k];
+            any = any || (li[t][q] != 0.0);
+        }
+    if (!any) return;
+    const Prim<double> W = A.node(FAM, i, j);
+    const double c = sqrt(gamma * W.p / W.r);
+    const double Z = W.r * c, iZ = 1.0 / Z;
+    NodeAcc<double> na;
+    na.zero();
+    node_wedges<FAM>(A, i, j, na);
+    double la[6][4];
+#pragma unroll
+    for (int ch = 0; ch < 6; ++ch)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) la[ch][m] = 0.0;
+    double lc = 0.0, lZ = 0.0, liZ = 0.0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const double lam = t ? lam1 : lam0;
+        const double r = c * lam;
+        double s[6], ds[6];
+#pragma unroll
+        for (int ch = 0; ch < 6; ++ch) {
+            s[ch] = ((na.a[ch][3] * r + na.a[ch][2]) * r + na.a[ch][1]) * r + na.a[ch][0];
+            ds[ch] = (3.0 * na.a[ch][3] * r + 2.0 * na.a[ch][2]) * r + na.a[ch][1];
+        }
+        // inc0 = r (s2 iZ + s3), inc1 = r (s4 iZ + s5), inc2 = r (s0 + Z s1)
+        double ls[6];
+        ls[2] = li[t][0] * r * iZ;
+        ls[3] = li[t][0] * r;
+        ls[4] = li[t][1] * r * iZ;
+        ls[5] = li[t][1] * r;
+        ls[0] = li[t][2] * r;
+        ls[1] = li[t][2] * r * Z;
+        double rp = 1.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+#pragma unroll
+            for (int ch = 0; ch < 6; ++ch) la[ch][m] += ls[ch] * rp;
+            rp *= r;
+        }
+        const double lr = li[t][0] * (s[2] * iZ + s[3] + r * (ds[2] * iZ + ds[3])) +
+                          li[t][1] * (s[4] * iZ + s[5] + r * (ds[4] * iZ + ds[5])) +
+                          li[t][2] * (s[0] + Z * s[1] + r * (ds[0] + Z * ds[1]));
+        lc += lam * lr;
+        liZ += li[t][0] * r * s[2] + li[t][1] * r * s[4];
+        lZ += li[t][2] * r * s[1];
+    }
+    lZ += -iZ * iZ * liZ;
+    // c = sqrt(gamma p / rho), Z = rho c
+    const double gK[4] = {lc * (-c / (2.0 * W.r)) + lZ * (0.5 * c), 0.0, 0.0,
+                          lc * (c / (2.0 * W.p)) + lZ * (W.r * c / (2.0 * W.p))};
+    O.node(FAM, i, j, gK);
+    if constexpr (FAM == F_V) {
+        wedge_adj<W_V_NE, 0, 0>(la, O, i, j);
+        wedge_adj<W_V_NW, 1, 0>(la, O, i - 1, j);
+        wedge_adj<W_V_SW, 1, 1>(la, O, i - 1, j - 1);
+        wedge_adj<W_V_SE, 0, 1>(la, O, i, j - 1);
+    } else if constexpr (FAM == F_EV) {
+        wedge_adj<W_EV_R, 0, 2>(la, O, i, j);
+        wedge_adj<W_EV_L, 1, 2>(la, O, i - 1, j);
+    } else if constexpr (FAM == F_EH) {
+        wedge_adj<W_EH_U, 2, 0>(la, O, i, j);
+        wedge_adj<W_EH_D, 2, 1>(la, O, i, j - 1);
+    } else {
+        wedge_adj<W_C, 2, 2>(la, O, i, j);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_adj_incr(StatePtrs<double> prim, const double* C, AdjOut O, double gamma,
+                                                  double lam0, double lam1) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= O.nx || j >= O.ny) return;
+    AdjNodes A{{}, C, O.nx, O.ny};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) A.s[k] = prim.p[k];
+    incr_adj<F_V>(A, O, i, j, gamma, lam0, lam1);
+    incr_adj<F_EV>(A, O, i, j, gamma, lam0, lam1);
+    incr_adj<F_EH>(A, O, i, j, gamma, lam0, lam1);
+    incr_adj<F_C>(A, O, i, j, gamma, lam0, lam1);
+}
+
+__device__ __forceinline__ void cons_T(const Prim<double>& w, double gamma, const double lU[4], double g[4]) {
+    // U = (rho, rho u, rho v, p/(gamma-1) + rho (u^2+v^2)/2)
+    const double q2 = 0.5 * (w.u * w.u + w.v * w.v);
+    g[0] = lU[0] + w.u * lU[1] + w.v * lU[2] + q2 * lU[3];
+    g[1] = w.r * lU[1] + w.r * w.u * lU[3];
+    g[2] = w.r * lU[2] + w.r * w.v * lU[3];
+    g[3] = lU[3] / (gamma - 1.0);
+}
+
+__global__ void __launch_bounds__(256) k_adj_centre(StatePtrs<double> prim, const double* C, StatePtrs<double> cot1,
+                                                    AdjOut O, double gamma) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= O.nx || j >= O.ny) return;
+    AdjNodes A{{}, C, O.nx, O.ny};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) A.s[k] = prim.p[k];
+    const size_t N = (size_t)O.nx * O.ny, c = A.idx(i, j);
+    const double lW[4] = {O.lC[c], O.lC[N + c], O.lC[2 * N + c], O.lC[3 * N + c]};
+    const Prim<double> Wc = A.node(F_C, i, j);
+    // W = prim(U_c): rho = U0, u = U1/U0, v = U2/U0, p = (g-1)(U3 - (U1 u + U2 v)/2)
+    const double ir = 1.0 / Wc.r, gm1 = gamma - 1.0;
+    double lU[4];
+    lU[0] = lW[0] - lW[1] * Wc.u * ir - lW[2] * Wc.v * ir + lW[3] * gm1 * 0.5 * (Wc.u * Wc.u + Wc.v * Wc.v);
+    lU[1] = lW[1] * ir - lW[3] * gm1 * Wc.u;
+    lU[2] = lW[2] * ir - lW[3] * gm1 * Wc.v;
+    lU[3] = lW[3] * gm1;
+    // U_c = 9/4 [Ubar - sum_corners U / 36 - sum_edges U / 9]
+#pragma unroll
+    for (int k = 0; k < 4; ++k) O.S[k][c] = cot1.p[k][c] + 2.25 * lU[k];
+    double lc[4], le[4], g[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { lc[k] = -lU[k] * (1.0 / 16.0); le[k] = -lU[k] * 0.25; }
+    cons_T(A.node(F_V, i, j), gamma, lc, g);          O.node(F_V, i, j, g);
+    cons_T(A.node(F_V, i + 1, j), gamma, lc, g);      O.node(F_V, i + 1, j, g);
+    cons_T(A.node(F_V, i, j + 1), gamma, lc, g);      O.node(F_V, i, j + 1, g);
+    cons_T(A.node(F_V, i + 1, j + 1), gamma, lc, g);  O.node(F_V, i + 1, j + 1, g);
+    cons_T(A.node(F_EH, i, j), gamma, le, g);         O.node(F_EH, i, j, g);
+    cons_T(A.node(F_EH, i, j + 1), gamma, le, g);     O.node(F_EH, i, j + 1, g);
+    cons_T(A.node(F_EV, i, j), gamma, le, g);         O.node(F_EV, i, j, g);
+    cons_T(A.node(F_EV, i + 1, j), gamma, le, g);     O.node(F_EV, i + 1, j, g);
+}
+
+hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1_[16], void* const cot0_[16]) {
+    dim3 blk(64, 4), grd((a.nx + 63) / 64, (a.ny + 3) / 4);
+    const size_t N = (size_t)a.nx * a.ny;
+    double* C = (double*)a.scratch;
+    double* Dfwd = C + 4 * N;
+    double* lC = Dfwd + 24 * N;
+    double* lD = lC + 4 * N;
+    StatePtrs<double> prim, cot1, cot0;
+    for (int k = 0; k < 16; ++k) {
+        prim.p[k] = (double*)a.in[k];
+        cot1.p[k] = (double*)cot1_[k];
+        cot0.p[k] = (double*)cot0_[k];
+    }
+    hipError_t e = launch_intermediates_f64(a, C, Dfwd);
+    if (e != hipSuccess) return e;
+    PlaneList L;
+    int np = 0;
+    for (int k = 4; k < 16; ++k) L.p[np++] = cot0.p[k];
+    for (int k = 0; k < 4; ++k) L.p[np++] = lC + k * N;
+    for (int k = 0; k < 24; ++k) L.p[np++] = lD + k * N;
+    hipLaunchKernelGGL(k_adj_zero_list, dim3(1024), dim3(256), 0, a.stream, L, np, N);
+    AdjOut O;
+    for (int k = 0; k < 16; ++k) O.S[k] = cot0.p[k];
+    O.lC = lC;
+    O.lD = lD;
+    O.nx = a.nx;
+    O.ny = a.ny;
+    const double lam1 = a.dt / a.h, lam0 = 0.5 * lam1;
+    if (a.ev_begin) (void)hipEventRecord(a.ev_begin, a.stream);
+    hipLaunchKernelGGL(k_adj_points, grd, blk, 0, a.stream, prim, C, Dfwd, cot1, O, a.gamma, lam0, lam1);
+    hipLaunchKernelGGL(k_adj_incr, grd, blk, 0, a.stream, prim, C, O, a.gamma, lam0, lam1);
+    hipLaunchKernelGGL(k_adj_centre, grd, blk, 0, a.stream, prim, C, cot1, O, a.gamma);
+    if (a.ev_end) (void)hipEventRecord(a.ev_end, a.stream);
+    return hipGetLastError();
+}
+
+size_t scratch_bytes_adjoint_f64(int nx, int ny) { return (size_t)nx * ny * (4 + 24 + 4 + 24) * sizeof(double); }
+
+}  // namespace af

@@ -34,6 +34,7 @@ struct af_ctx {
     bool f32;              // AF_F32 context: float perturbation planes about cfg.bg
     void* comp;            // AF_F32: 4 float compensation planes of the average update
     const void* traj[2];   // AF_F32: the buffers of the trajectory the compensation belongs to
+    void* adj_scratch;     // AF_F64: forward intermediates and reverse accumulators of af_step_adjoint
     int variant;           // 0: fused LDS-tiled kernel, 1: multi-kernel path, 2: two-launch split
 };
 
@@ -205,6 +206,7 @@ void af_destroy(af_ctx* c) {
     if (c->partials) (void)hipFree(c->partials);
     if (c->diag_out) (void)hipFree(c->diag_out);
     if (c->comp) (void)hipFree(c->comp);
+    if (c->adj_scratch) (void)hipFree(c->adj_scratch);
     for (int k = 0; k < 2; ++k)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     delete c;
@@ -264,8 +266,24 @@ af_status af_read_status(af_ctx* c, af_status* status) {
 af_status af_step_adjoint(af_ctx* c, const af_state* primal_n, const af_state* cot_np1, af_state* cot_n,
                           double dt) {
     if (!c || !state_ok(primal_n) || !state_ok(cot_np1) || !state_ok(cot_n) || !(dt > 0.0)) return AF_ERR_ARG;
-    if (c->f32) return AF_ERR_UNSUPPORTED;
-    return AF_ERR_UNSUPPORTED;
+    if (c->f32 || (c->cfg.flags & AF_SCHEME_RB)) return AF_ERR_UNSUPPORTED;
+    if (!c->adj_scratch) AF_HIP(hipMalloc(&c->adj_scratch, af::scratch_bytes_adjoint_f64(c->cfg.nx, c->cfg.ny)));
+    af::StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nx = c->cfg.nx;
+    a.ny = c->cfg.ny;
+    a.h = c->cfg.h;
+    a.gamma = c->cfg.gamma;
+    a.dt = dt;
+    planes_of(primal_n, a.in);
+    a.scratch = c->adj_scratch;
+    a.status = c->status;
+    a.stream = c->stream;
+    void *p1[16], *p0[16];
+    planes_of(cot_np1, p1);
+    planes_of(cot_n, p0);
+    AF_HIP(af::launch_adjoint_f64(a, p1, p0));
+    return AF_OK;
 }
 
 af_status af_diagnostics(af_ctx* c, const af_state* s, double dt, af_diag* out) {

@@ -1,0 +1,104 @@
+"""FP64 adjoint step (af_step_adjoint) against the oracle.
+
+* exact parity: on a small grid the oracle's full Jacobian is assembled column by
+  column from complex-step JVPs (exact to round-off) and J^T lambda compared with
+  the GPU adjoint element by element;
+* dot-product test on a larger grid: <lambda, J v> (oracle JVP) = <J^T lambda, v> (GPU);
+* checkpointed rollout gradient against central finite differences (GPU forward).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2605_12915_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+def gpu_adjoint(torch_dev, P, s0, lam, dt):
+    torch, dev = torch_dev
+    from paper_2605_12915_amd.stepper import Stepper
+    st = Stepper(P.nx, P.ny, P.h, P.gamma, device=dev)
+    g = st.adjoint(torch.from_numpy(s0).to(dev), torch.from_numpy(np.ascontiguousarray(lam)).to(dev), dt)
+    torch.cuda.synchronize()
+    return g.cpu().numpy()
+
+
+@pytest.mark.parametrize("nx,ny,seed", [(6, 5, 1), (7, 8, 2)])
+def test_adjoint_exact_vs_oracle_jacobian(torch_dev, orc, nx, ny, seed):
+    P = I.random_smooth(nx, ny, seed=seed, amp=0.15, vel=(0.35, -0.25))
+    s0 = P.state()
+    dt = P.dt_for_cfl(0.45)
+    n = s0.size
+    J = np.zeros((n, n))
+    e = np.zeros(n)
+    for k in range(n):
+        e[:] = 0.0
+        e[k] = 1.0
+        _, jv = orc.step_jvp(s0, e.reshape(s0.shape), P.h, P.gamma, dt, threads=1)
+        J[:, k] = jv.ravel()
+    rng = np.random.default_rng(seed)
+    lam = rng.normal(size=s0.shape)
+    want = (J.T @ lam.ravel()).reshape(s0.shape)
+    got = gpu_adjoint(torch_dev, P, s0, lam, dt)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print("adjoint vs oracle J^T lambda: max rel", err)
+    assert err < 1e-11
+
+
+def test_adjoint_dot_product(torch_dev, orc):
+    P = I.isentropic_vortex(32, uinf=(1.0, 1.0))
+    s0 = P.state()
+    dt = P.dt_for_cfl(0.4)
+    rng = np.random.default_rng(7)
+    for _ in range(3):
+        v = rng.normal(size=s0.shape)
+        lam = rng.normal(size=s0.shape)
+        _, jv = orc.step_jvp(s0, v, P.h, P.gamma, dt)
+        lhs = float(np.sum(lam * jv))
+        rhs = float(np.sum(gpu_adjoint(torch_dev, P, s0, lam, dt) * v))
+        assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + np.sqrt(np.sum(lam ** 2) * np.sum(jv ** 2)) * 1e-3)
+
+
+def test_rollout_gradient_vs_fd(torch_dev):
+    """Gradient of a quadratic functional of the final state w.r.t. the initial
+    density planes through 40 steps (checkpoints every 8) against central FD."""
+    torch, dev = torch_dev
+    from paper_2605_12915_amd.autodiff import rollout
+    from paper_2605_12915_amd.stepper import Stepper
+    P = I.acoustic_pulse_adjoint(48, width=0.15)
+    s0 = P.state()
+    dt = P.dt_for_cfl(0.4)
+    st = Stepper(P.nx, P.ny, P.h, P.gamma, device=dev)
+    x0 = torch.from_numpy(s0).to(dev)
+    w = torch.from_numpy(np.random.default_rng(3).normal(size=s0.shape)).to(dev)
+
+    def J(x):
+        return torch.sum(w * (rollout(x, st, dt, 40, 8) - x0) ** 2)
+
+    x = x0.clone().requires_grad_(True)
+    val = J(x)
+    val.backward()
+    grad = x.grad.detach()
+    rho_planes = [0, 4, 8, 12]
+    rng = np.random.default_rng(11)
+    for _ in range(3):
+        d = torch.zeros_like(x0)
+        for p in rho_planes:
+            d[p] = torch.from_numpy(rng.normal(size=s0.shape[1:])).to(dev)
+        eps = 1e-6
+        with torch.no_grad():
+            fd = (J(x0 + eps * d) - J(x0 - eps * d)) / (2 * eps)
+        ad = torch.sum(grad * d)
+        rel = abs(float(fd - ad)) / max(abs(float(ad)), 1e-30)
+        print("rollout FD check: ad", float(ad), "fd", float(fd), "rel", rel)
+        assert rel < 1e-6
