@@ -1,11 +1,21 @@
 """Benchmark of the RB-TAI Active Flux step on one MI355X.
 
-Workload (N = 1): periodic 2048 x 2048 grid, FP64, background rho = 1, p = 1/1.4,
+Headline (N = 1): periodic 2048 x 2048 grid, FP64, background rho = 1, p = 1/1.4,
 (u, v) = (0.5, 0.3) plus 16 seeded Fourier modes per primitive field (wavenumbers
-up to 8, amplitude 1e-3), CFL 0.4.  Inputs are generated on the host, copied to HBM
-before the timed region; K steps are timed between two device synchronisations.
+up to 8, amplitude 1e-3), CFL 0.4.  Inputs are generated on the host and copied to
+HBM before the timed region; K steps are timed between two device synchronisations.
 
-Prints ONE JSON line (see the design doc for every field's definition).
+The same run measures the three forms built on the step (in "forms"):
+  fp32     4096^2 isentropic vortex and 4096^2 Gaussian pulse, 500 FP32 steps each,
+           throughput and per-field error against the FP64 GPU path;
+  adjoint  512^2 acoustic pulse: adjoint-step / forward-step time, the full gradient
+           of an annulus acoustic energy through 200 steps (checkpoints every 20)
+           and its central finite-difference check in 8 density directions;
+  batch    64 double shear layers of seeded sizes N in [32, 1024], 1000 FP32 steps
+           in one hipGraph of persistent launches; aggregate rate, tuning table and
+           per-size-class rates.
+
+Prints ONE JSON line; progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -20,6 +30,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+PLANE_NAMES = [f"{fam}.{v}" for fam, vs in (("avg", ("rho", "rhou", "rhov", "E")), ("V", ("rho", "u", "v", "p")),
+                                              ("EV", ("rho", "u", "v", "p")), ("EH", ("rho", "u", "v", "p")))
+               for v in vs]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
 
 
 def parse():
@@ -28,6 +45,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--forms", default="fp32,adjoint,batch",
+                    help="comma list of forms to measure after the headline (or 'none')")
+    ap.add_argument("--fp32-n", type=int, default=4096)
+    ap.add_argument("--fp32-steps", type=int, default=500)
+    ap.add_argument("--adj-n", type=int, default=512)
+    ap.add_argument("--adj-steps", type=int, default=200)
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=512)
     ap.add_argument("--cpu-sample-steps", type=int, default=6)
@@ -52,6 +77,214 @@ def cpu_baseline(n: int, steps: int):
             "sample": f"{n}x{n} Fourier-mode flow, {steps} steps, FP64, {threads} OpenMP threads, {el:.2f} s"}
 
 
+def timed(torch, fn):
+    """Wall time of fn() between two device synchronisations."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+# ---------------------------------------------------------------------------------
+# FP32 precision form
+# ---------------------------------------------------------------------------------
+def abs_from_pert(torch, x32, bg, gamma):
+    """FP32 perturbation planes -> absolute FP64 planes (on the device)."""
+    from paper_2605_12915_amd.stepper import background_cons
+    off = list(background_cons(bg, gamma)) + [float(b) for b in bg] * 3
+    return x32.double() + torch.tensor(off, dtype=torch.float64, device=x32.device)[:, None, None]
+
+
+def form_fp32(torch, dev, n, steps):
+    from paper_2605_12915_amd import inputs as I
+    from paper_2605_12915_amd import perf
+    from paper_2605_12915_amd.stepper import Stepper, to_perturbation
+    out = {}
+    for tag, P in (("3a_isentropic_vortex", I.isentropic_vortex(n, uinf=(1.0, 1.0))),
+                   ("3b_gaussian_pulse", I.gaussian_pulse(n, amp=0.1, width=0.05))):
+        log(f"fp32 {tag}: generating {n}x{n} input")
+        s0 = P.state()
+        dt = P.dt_for_cfl(0.4)
+        ncell = P.nx * P.ny
+        # FP64 reference on the GPU (its parity with the oracle is the FP64 tests' bar)
+        st64 = Stepper(P.nx, P.ny, P.h, P.gamma, device=dev)
+        x64 = torch.from_numpy(s0).to(dev)
+        el64 = timed(torch, lambda: st64.step(x64, dt, steps))
+        st64.close()
+        st32 = Stepper(P.nx, P.ny, P.h, P.gamma, precision="f32", bg=P.bg, device=dev)
+        x32 = torch.from_numpy(to_perturbation(s0, P.bg, P.gamma)).to(dev)
+        del s0
+        st32.step(x32.clone(), dt, 3)                       # warm-up on a copy
+        el32 = timed(torch, lambda: st32.step(x32, dt, steps))
+        status = st32.read_status()
+        _, ker_ms = st32.time_steps(x32, dt, 20)
+        kname = st32.dominant_kernel()
+        st32.close()
+        got = abs_from_pert(torch, x32, P.bg, P.gamma)
+        del x32
+        per = {}
+        worst_l2 = worst_linf = 0.0
+        for k in range(16):
+            r = x64[k]
+            e = got[k] - r
+            l2 = float(torch.linalg.vector_norm(e) / max(float(torch.linalg.vector_norm(r - r.mean())), 1e-300))
+            linf = float(e.abs().max() / max(float(r.max() - r.min()), 1e-300))
+            per[PLANE_NAMES[k]] = {"l2_rel": l2, "linf_rel": linf}
+            worst_l2, worst_linf = max(worst_l2, l2), max(worst_linf, linf)
+        del got, x64
+        torch.cuda.empty_cache()
+        flops = perf.ALGO_FLOPS_PER_CELL_F64 * ncell
+        ach = flops / (ker_ms * 1e-3) / 1e12
+        out[tag] = {
+            "nx": P.nx, "ny": P.ny, "steps": steps, "dt": dt, "status": status,
+            "value": ncell * steps / el32 / 1e6, "unit": "Mcell-updates/s",
+            "fp64_value": ncell * steps / el64 / 1e6, "speedup_vs_fp64": el64 / el32,
+            "kernel": kname, "kernel_ms": ker_ms,
+            "roofline": {"bound": "alu", "achieved": ach, "peak": perf.FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": ach / perf.FP32_PEAK_TFLOPS,
+                         "hbm_gbs_algorithmic": perf.ALGO_BYTES_PER_CELL_F32 * ncell / (ker_ms * 1e-3) / 1e9},
+            "error_vs_fp64": {"max_l2_rel": worst_l2, "max_linf_rel": worst_linf,
+                              "definition": "per plane: ||e||_2 / ||ref - mean(ref)||_2 and max|e| / range(ref)",
+                              "per_plane": per},
+        }
+        log(f"fp32 {tag}: {out[tag]['value']:.0f} Mcell/s, max linf_rel {worst_linf:.2e}")
+    return out
+
+
+# ---------------------------------------------------------------------------------
+# Differentiation form
+# ---------------------------------------------------------------------------------
+def form_adjoint(torch, dev, n, steps, every=20, ndir=8):
+    import numpy as np
+
+    from paper_2605_12915_amd import inputs as I
+    from paper_2605_12915_amd.autodiff import rollout
+    from paper_2605_12915_amd.stepper import Stepper
+    P = I.acoustic_pulse_adjoint(n)
+    s0 = P.state()
+    dt = P.dt_for_cfl(0.4)
+    g = P.gamma
+    st = Stepper(P.nx, P.ny, P.h, g, device=dev)
+    x0 = torch.from_numpy(s0).to(dev)
+    # per-call times of the forward step and the adjoint step (same state)
+    K = 50
+    y = torch.empty_like(x0)
+    cot = torch.from_numpy(np.random.default_rng(1).normal(size=s0.shape)).to(dev)
+    gout = torch.empty_like(x0)
+    st.step_out(x0, dt, y)
+    st.adjoint(x0, cot, dt, gout)
+    t_fwd = timed(torch, lambda: [st.step_out(x0, dt, y) for _ in range(K)]) / K
+    t_adj = timed(torch, lambda: [st.adjoint(x0, cot, dt, gout) for _ in range(K)]) / K
+    # annulus acoustic energy from cell-average primitives
+    c = (np.arange(n) + 0.5) * P.h
+    X, Y = np.meshgrid(c, c)
+    r = np.sqrt((X - 0.5) ** 2 + (Y - 0.5) ** 2)
+    mask = torch.from_numpy(((r >= 0.10) & (r <= 0.20)).astype(np.float64)).to(dev)
+    rho0, p0 = P.bg[0], P.bg[3]
+    c0sq = g * p0 / rho0
+
+    def J(x):
+        U = x[:4]
+        rho = U[0]
+        u, v = U[1] / rho, U[2] / rho
+        p = (g - 1.0) * (U[3] - 0.5 * rho * (u * u + v * v))
+        e = (p - p0) ** 2 / (2.0 * rho0 * c0sq) + 0.5 * rho0 * (u * u + v * v)
+        return P.h * P.h * torch.sum(mask * e)
+
+    def J_of_initial(x):
+        z = x.clone()
+        st.step(z, dt, steps)
+        return float(J(z))
+
+    xg = x0.clone().requires_grad_(True)
+
+    def grad():
+        val = J(rollout(xg, st, dt, steps, every))
+        val.backward()
+        return val
+
+    t_grad = timed(torch, grad)
+    t_fwd_roll = timed(torch, lambda: J_of_initial(x0))
+    G = xg.grad.detach()
+    rng = np.random.default_rng(8)
+    rho_planes = [0, 4, 8, 12]
+    eps = 1e-6 * float(x0[rho_planes].abs().max())
+    errs = []
+    with torch.no_grad():
+        for _ in range(ndir):
+            d = torch.zeros_like(x0)
+            for pl in rho_planes:
+                d[pl] = torch.from_numpy(rng.normal(size=s0.shape[1:])).to(dev)
+            fd = (J_of_initial(x0 + eps * d) - J_of_initial(x0 - eps * d)) / (2.0 * eps)
+            ad = float(torch.sum(G * d))
+            errs.append(abs(fd - ad) / max(abs(ad), 1e-300))
+    st.close()
+    out = {"nx": n, "ny": n, "dt": dt, "forward_step_ms": t_fwd * 1e3, "adjoint_step_ms": t_adj * 1e3,
+           "adjoint_over_forward": t_adj / t_fwd, "gradient_steps": steps, "checkpoint_every": every,
+           "gradient_ms": t_grad * 1e3, "forward_rollout_ms": t_fwd_roll * 1e3,
+           "gradient_over_forward_rollout": t_grad / t_fwd_roll,
+           "fd_check": {"directions": ndir, "eps": eps, "max_rel_err": max(errs),
+                        "subspace": "the four density planes of the initial state"}}
+    log(f"adjoint: ratio {out['adjoint_over_forward']:.2f}, FD max rel {max(errs):.2e}")
+    return out
+
+
+# ---------------------------------------------------------------------------------
+# Batching form
+# ---------------------------------------------------------------------------------
+def form_batch(torch, dev, count, steps, big_fp32_rate):
+    from paper_2605_12915_amd import inputs as I
+    from paper_2605_12915_amd.stepper import Batch, Stepper, to_perturbation
+    sizes = I.batch_sizes(count)
+    log(f"batch: generating {count} inputs, {sum(n * n for n in sizes)} cells")
+    Ps = [I.double_shear_layer(N) for N in sizes]
+    dts = [P.dt_for_cfl(0.4) for P in Ps]
+    xs0 = [torch.from_numpy(to_perturbation(P.state(), P.bg, P.gamma)).to(dev) for P in Ps]
+    grids = [dict(nx=P.nx, ny=P.ny, h=P.h, gamma=P.gamma, bg=P.bg) for P in Ps]
+
+    def run_batch(idx, nsteps):
+        b = Batch([grids[k] for k in idx], device=dev)
+        xs = [xs0[k].clone() for k in idx]
+        b.step(xs, [dts[k] for k in idx], nsteps)          # tuning + capture + first replay
+        el = timed(torch, lambda: b.step(xs, [dts[k] for k in idx], nsteps))
+        info, status = b.info(), b.read_status()
+        b.close()
+        return sum(sizes[k] ** 2 for k in idx) * nsteps / el / 1e6, el, info, status
+
+    allidx = list(range(count))
+    rate, el, info, status = run_batch(allidx, steps)
+    # the same instances stepped one by one (one launch per instance and step)
+    sts = [Stepper(P.nx, P.ny, P.h, P.gamma, precision="f32", bg=P.bg, device=dev) for P in Ps]
+    ys = [x.clone() for x in xs0]
+    k1 = max(1, steps // 10)
+    for s_, y, dt in zip(sts, ys, dts):
+        s_.step(y, dt, 1)
+    el1 = timed(torch, lambda: [s_.step(y, dt, k1) for s_, y, dt in zip(sts, ys, dts)])
+    for s_ in sts:
+        s_.close()
+    ncells = sum(n * n for n in sizes)
+    classes = []
+    edges = [32, 64, 128, 256, 512, 1025]
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        idx = [k for k in allidx if lo <= sizes[k] < hi]
+        if not idx:
+            continue
+        r_, _, inf_, _ = run_batch(idx, max(100, steps // 5))
+        classes.append({"sizes": [lo, hi - 1], "instances": len(idx), "cells": sum(sizes[k] ** 2 for k in idx),
+                        "batched_mcells": r_, "tile": inf_["chosen"],
+                        "efficiency_vs_large_grid_fp32": r_ / big_fp32_rate if big_fp32_rate else None})
+    out = {"instances": count, "sizes_min_max": [min(sizes), max(sizes)], "cells": ncells, "steps": steps,
+           "value": rate, "unit": "Mcell-updates/s", "seconds": el, "status": status,
+           "launches_per_step": 1, "graph_launches": steps + (steps & 1),
+           "tuning": info, "one_by_one_mcells": ncells * k1 / el1 / 1e6,
+           "speedup_vs_one_by_one": rate / (ncells * k1 / el1 / 1e6),
+           "efficiency_vs_large_grid_fp32": rate / big_fp32_rate if big_fp32_rate else None,
+           "size_classes": classes}
+    log(f"batch: {rate:.0f} Mcell/s aggregate, one-by-one {out['one_by_one_mcells']:.0f}")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -61,9 +294,11 @@ def main():
     import torch
 
     from paper_2605_12915_amd import inputs as I
+    from paper_2605_12915_amd import perf
     from paper_2605_12915_amd.stepper import Stepper
 
     dev = torch.device("cuda:0")
+    log(f"headline: generating {args.n}x{args.n} input")
     P = I.fourier_modes(args.n)
     s0 = P.state()
     dt = P.dt_for_cfl(0.4)
@@ -72,24 +307,20 @@ def main():
     torch.cuda.synchronize()
     if args.warmup:
         st.step(x, dt, args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st.step(x, dt, args.steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    el = timed(torch, lambda: st.step(x, dt, args.steps))
     ncell = P.nx * P.ny
     value = ncell * args.steps / el / 1e6
     # dominant-kernel duration from HIP events on the library's stream
     tot_ms, ker_ms = st.time_steps(x, dt, 20)
     diag = st.diagnostics(x, dt)
     ok = bool(np.isfinite(diag["mass"]))
-    from paper_2605_12915_amd import perf
     kname = st.dominant_kernel()
     flops = perf.ALGO_FLOPS_PER_CELL_F64 * ncell            # per launch of the step kernel
     achieved = flops / (ker_ms * 1e-3) / 1e12
     t_alu = flops / (perf.FP64_PEAK_TFLOPS * 1e12)
     t_hbm = perf.ALGO_BYTES_PER_CELL_F64 * ncell / (perf.HBM_PEAK_GBS * 1e9)
     tr = perf.stored_traffic(kname)
+    log(f"headline: {value:.0f} Mcell/s, kernel {ker_ms:.3f} ms")
     line = {
         "metric": "Mcell-updates/s per AF step (FP64 vs FP32) at stated error; adjoint/forward ratio",
         "value": value, "unit": "Mcell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -107,13 +338,29 @@ def main():
                      "t_alu_ms": t_alu * 1e3, "t_hbm_ms": t_hbm * 1e3},
         "finite": ok,
     }
+    st.close()
+    del x
+    torch.cuda.empty_cache()
     if args.copy_probe:
         src = torch.empty(128 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)   # 1 GiB
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+        del src, dst
+    forms = [f for f in args.forms.split(",") if f and f != "none"]
+    if forms:
+        line["forms"] = {}
+    big32 = None
+    if "fp32" in forms:
+        line["forms"]["fp32"] = form_fp32(torch, dev, args.fp32_n, args.fp32_steps)
+        big32 = line["forms"]["fp32"]["3b_gaussian_pulse"]["value"]
+    if "adjoint" in forms:
+        line["forms"]["adjoint"] = form_adjoint(torch, dev, args.adj_n, args.adj_steps)
+    if "batch" in forms:
+        line["forms"]["batch"] = form_batch(torch, dev, args.batch_count, args.batch_steps, big32)
     if not args.no_cpu_baseline:
+        log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, args.cpu_sample_steps)
     print(json.dumps(line))
 

@@ -125,6 +125,39 @@ af_status af_diagnostics(af_ctx* ctx, const af_state* s, double dt, af_diag* out
 af_status af_time_steps(af_ctx* ctx, const af_state* s, double dt, int32_t nsteps,
                         double* total_ms, double* kernel_ms);
 
+/* Batching form.  n grids (each described by its own af_config; all AF_F32, TAI
+ * scheme) stepped together: every step is ONE persistent kernel launch over the
+ * list of (grid, tile) work items of the whole batch, and af_step_batch replays
+ * nsteps such launches captured in a hipGraph (built on first use for each nsteps
+ * and kept).  The tile shape is chosen by an autotuner on the first af_step_batch
+ * call: every compiled tile configuration is timed on a copy of the batch's states
+ * and the fastest is kept (af_batch_info reports the timings); the environment
+ * variable AF_BATCH_TILE=k (0 <= k < 6), read by af_init_batch, fixes candidate k
+ * instead (candidates, cells x cells / threads per workgroup: 32x8/512, 32x8/256,
+ * 32x16/512, 32x16/256, 64x8/512, 16x16/256).  Each grid keeps its
+ * own Kahan compensation planes, tied to the trajectory as for AF_F32 contexts.
+ * The library allocates one partner state and four compensation planes per grid.
+ * hip_stream is borrowed; replays run on an internal stream ordered after it. */
+af_status af_init_batch(const af_config* cfgs, int32_t n, void* hip_stream, af_ctx** out);
+/* (af_init_batch errors: AF_ERR_ARG for n outside 1..4096 or a config af_init would
+ * reject; AF_ERR_UNSUPPORTED for a config that is not AF_F32 or asks for
+ * AF_SCHEME_RB.  Configs are checked before any HIP call.) */
+
+/* Advance every grid q of a batch context by nsteps (1..65536) steps of size dts[q]
+ * in place; states[q] are caller-owned float perturbation planes (layout as above).
+ * The result for grid q is the one af_step gives on an AF_F32 context of cfgs[q].
+ * The library's descriptor copy is re-uploaded (one host synchronisation) only when
+ * a state pointer or dt changed since the previous call.  With AF_CHECK in
+ * cfgs[0].flags the status of the whole batch is read back after the call (no
+ * rollback).  Errors: AF_ERR_ARG for bad pointers or dts, AF_ERR_UNSUPPORTED on a
+ * single-grid context (and the single-grid calls return it on a batch context). */
+af_status af_step_batch(af_ctx* ctx, af_state* states, const double* dts, int32_t nsteps);
+
+/* JSON text describing a batch context's work list and tuning (chosen tile shape and
+ * the measured ms per step of every candidate) into buf (NUL-terminated, truncated
+ * to buflen); returns the full length, or -1 for a non-batch context. */
+int32_t af_batch_info(af_ctx* ctx, char* buf, int32_t buflen);
+
 void af_destroy(af_ctx* ctx);
 const char* af_status_string(af_status s);
 int32_t af_last_hip_error(void);

@@ -15,6 +15,7 @@ AF_CHECK, AF_SCHEME_RB = 1, 2
 EXPORTED = [
     "af_init", "af_step", "af_step_out", "af_read_status", "af_step_adjoint", "af_diagnostics",
     "af_time_steps", "af_destroy", "af_status_string", "af_last_hip_error", "af_dominant_kernel",
+    "af_init_batch", "af_step_batch", "af_batch_info",
 ]
 
 
@@ -70,10 +71,15 @@ def lib() -> ctypes.CDLL:
         L.af_status_string.argtypes = [I32]
         L.af_status_string.restype = ctypes.c_char_p
         L.af_last_hip_error.restype = I32
+        L.af_init_batch.argtypes = [ctypes.POINTER(AfConfig), I32, P, ctypes.POINTER(P)]
+        L.af_step_batch.argtypes = [P, ctypes.POINTER(AfState), ctypes.POINTER(D), I32]
+        L.af_batch_info.argtypes = [P, ctypes.c_char_p, I32]
+        L.af_batch_info.restype = I32
         L.af_dominant_kernel.argtypes = [P]
         L.af_dominant_kernel.restype = ctypes.c_char_p
         for name in EXPORTED:
-            if name not in ("af_destroy", "af_status_string", "af_last_hip_error", "af_dominant_kernel"):
+            if name not in ("af_destroy", "af_status_string", "af_last_hip_error", "af_dominant_kernel",
+                            "af_batch_info"):
                 getattr(L, name).restype = I32
         _LIB = L
     return _LIB

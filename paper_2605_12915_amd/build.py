@@ -19,15 +19,19 @@ ARCH = os.environ.get("AF_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = "/opt/rocm/bin/hipcc"
 FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=fast",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics", f"-I{CSRC}", f"-I{INCLUDE}",
 ]
+# FP contraction: free (across statements) for the FP64 kernels; within source
+# expressions only for the two FP32 step kernels, which must round identically.
+CONTRACT_ON = {"af_fused_f32.hip", "af_batch.hip"}
 
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    contract = "-ffp-contract=on" if os.path.basename(src) in CONTRACT_ON else "-ffp-contract=fast"
+    cmd = [HIPCC, *FLAGS, contract, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

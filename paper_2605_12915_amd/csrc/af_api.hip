@@ -2,12 +2,17 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <cstdio>
+#include <map>
+#include <string>
 #include <vector>
 
 #include "af.h"
+#include "af_batch.h"
 #include "af_internal.h"
 
 namespace {
@@ -19,23 +24,39 @@ constexpr int kDiagPartials = 1024;
 }  // namespace
 
 struct af_ctx {
-    af_config cfg;
-    hipStream_t stream;
-    int device;
-    size_t N;
-    size_t elem;           // bytes per state element
-    void* state2;          // second state for ping-ponging (16 planes)
-    void* state3;          // third state, only for af_time_steps
-    void* scratch;         // path scratch
-    unsigned* status;      // device status bits
-    double* partials;      // diagnostics partials
-    double* diag_out;      // 9 doubles on the device
-    hipEvent_t ev[4];      // [0], [1]: owned; [2], [3]: slots for per-launch timing events
-    bool f32;              // AF_F32 context: float perturbation planes about cfg.bg
-    void* comp;            // AF_F32: 4 float compensation planes of the average update
-    const void* traj[2];   // AF_F32: the buffers of the trajectory the compensation belongs to
-    void* adj_scratch;     // AF_F64: forward intermediates and reverse accumulators of af_step_adjoint
-    int variant;           // 0: fused LDS-tiled kernel, 1: multi-kernel path, 2: two-launch split
+    af_config cfg{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    size_t N = 0;
+    size_t elem = 0;               // bytes per state element
+    void* state2 = nullptr;        // second state for ping-ponging (16 planes)
+    void* state3 = nullptr;        // third state, only for af_time_steps
+    void* scratch = nullptr;       // path scratch
+    unsigned* status = nullptr;    // device status bits
+    double* partials = nullptr;    // diagnostics partials
+    double* diag_out = nullptr;    // 9 doubles on the device
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // [0], [1] owned; [2], [3] per-launch timing slots
+    bool f32 = false;              // AF_F32 context: float perturbation planes about cfg.bg
+    void* comp = nullptr;          // AF_F32: 4 float compensation planes of the average update
+    const void* traj[2] = {nullptr, nullptr};  // AF_F32: buffers of the trajectory the compensation belongs to
+    void* adj_scratch = nullptr;   // AF_F64: forward intermediates and reverse accumulators of af_step_adjoint
+    int variant = 0;               // 0: fused LDS-tiled kernel, 1: multi-kernel path, 2: two-launch split
+    // ---- batching form (af_init_batch) ----
+    int nbatch = 0;                          // 0 for a single-grid context
+    std::vector<af_config> bcfg;
+    std::vector<af::BatchInst> binst;        // host copy of the descriptors
+    std::vector<af::BatchInst> bup;          // descriptors as last uploaded
+    int force_cfg = -1;
+    std::string kname;                       // af_dominant_kernel's text for batch contexts                      // AF_BATCH_TILE: fixed tile configuration, no tuning
+    af::BatchInst* d_binst = nullptr;
+    std::vector<void*> bbufs;                // per-instance partner states and compensation planes
+    std::vector<const void*> btraj;          // per-instance state of the current trajectory
+    int2* d_work = nullptr;
+    int nwork = 0, tune_cfg = -1, grid = 0;
+    double tune_ms[af::kNumBatchCfgs] = {0, 0, 0, 0};
+    hipStream_t cap = nullptr;               // internal stream for graph capture and replay
+    hipEvent_t bev[2] = {nullptr, nullptr};
+    std::map<int, hipGraphExec_t> graphs;    // nsteps -> instantiated graph
 };
 
 #define AF_HIP(x)                                       \
@@ -129,6 +150,114 @@ af_status read_status(af_ctx* c, unsigned* bits) {
     return AF_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batching form
+// ---------------------------------------------------------------------------
+// Work list of (instance, tile) for tile configuration `cfg`.
+hipError_t batch_build_work(af_ctx* c, int cfg) {
+    const af::BatchTileCfg t = af::kBatchCfgs[cfg];
+    std::vector<int2> w;
+    for (int q = 0; q < c->nbatch; ++q) {
+        af::BatchInst& d = c->binst[q];
+        d.tiles_x = (d.nx + t.tx - 1) / t.tx;
+        d.ntiles = d.tiles_x * ((d.ny + t.ty - 1) / t.ty);
+        for (int k = 0; k < d.ntiles; ++k) w.push_back(make_int2(q, k));
+    }
+    if (c->d_work) { hipError_t e = hipFree(c->d_work); if (e != hipSuccess) return e; c->d_work = nullptr; }
+    hipError_t e = hipMalloc((void**)&c->d_work, w.size() * sizeof(int2));
+    if (e == hipSuccess) e = hipMemcpy(c->d_work, w.data(), w.size() * sizeof(int2), hipMemcpyHostToDevice);
+    c->nwork = (int)w.size();
+    int per_cu = 1;
+    if (e == hipSuccess) e = af::batch_occupancy(cfg, &per_cu);
+    hipDeviceProp_t prop;
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, c->device);
+    c->grid = (per_cu > 0 ? per_cu : 1) * prop.multiProcessorCount;
+    return e;
+}
+
+// Upload the descriptors when they changed (new state pointers, dt, tile shape).
+// Synchronous: the host vector may change again on the next call.
+hipError_t batch_upload(af_ctx* c, hipStream_t s) {
+    const size_t bytes = c->nbatch * sizeof(af::BatchInst);
+    if (c->bup.size() == c->binst.size() && std::memcmp(c->bup.data(), c->binst.data(), bytes) == 0)
+        return hipSuccess;
+    hipError_t e = hipMemcpyAsync(c->d_binst, c->binst.data(), bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) c->bup = c->binst;
+    return e;
+}
+
+// Autotuner: time every tile configuration on the batch itself (a copy of the
+// caller's states stepped between two library-owned buffers), keep the fastest.
+hipError_t batch_tune(af_ctx* c) {
+    std::vector<af::BatchInst> saved = c->binst;
+    std::vector<void*> tmp;
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < c->nbatch && e == hipSuccess; ++q) {
+        af::BatchInst& d = c->binst[q];
+        const size_t N = (size_t)d.nx * d.ny;
+        void *t1 = nullptr, *t2 = nullptr;
+        e = hipMalloc(&t1, 16 * N * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(&t2, 4 * N * sizeof(float));
+        if (e == hipSuccess) e = hipMemsetAsync(t2, 0, 4 * N * sizeof(float), c->stream);
+        tmp.push_back(t1);
+        tmp.push_back(t2);
+        for (int k = 0; k < 16 && e == hipSuccess; ++k)
+            e = hipMemcpyAsync(d.S[1][k], saved[q].S[0][k], N * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
+        for (int k = 0; k < 16; ++k) {
+            d.S[0][k] = d.S[1][k];
+            d.S[1][k] = (float*)t1 + (size_t)k * N;
+        }
+        d.comp = (float*)t2;
+    }
+    int best = 0;
+    for (int cfg = 0; cfg < af::kNumBatchCfgs && e == hipSuccess; ++cfg) {
+        e = batch_build_work(c, cfg);
+        if (e == hipSuccess) e = batch_upload(c, c->stream);
+        const int warm = 2, reps = 4;
+        for (int r = 0; r < warm && e == hipSuccess; ++r)
+            e = af::launch_batch(cfg, c->d_binst, c->d_work, c->nwork, r & 1, c->status, c->grid, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(c->ev[0], c->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            e = af::launch_batch(cfg, c->d_binst, c->d_work, c->nwork, r & 1, c->status, c->grid, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(c->ev[1], c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(c->ev[1]);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+        c->tune_ms[cfg] = ms / reps;
+        if (c->tune_ms[cfg] < c->tune_ms[best]) best = cfg;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    for (void* p : tmp)
+        if (p) (void)hipFree(p);
+    c->binst = saved;
+    if (e == hipSuccess) {
+        c->tune_cfg = best;
+        e = batch_build_work(c, best);
+    }
+    // the tuning runs leave status bits of scratch data: clear them
+    if (e == hipSuccess) e = hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream);
+    return e;
+}
+
+hipError_t batch_graph(af_ctx* c, int nsteps, hipGraphExec_t* out) {
+    auto it = c->graphs.find(nsteps);
+    if (it != c->graphs.end()) { *out = it->second; return hipSuccess; }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+    for (int k = 0; k < nsteps && e == hipSuccess; ++k)
+        e = af::launch_batch(c->tune_cfg, c->d_binst, c->d_work, c->nwork, k & 1, c->status, c->grid, c->cap);
+    if (e == hipSuccess && (nsteps & 1)) e = af::launch_batch_copy(c->d_binst, c->nbatch, c->cap);
+    hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+    if (e == hipSuccess) e = e2;
+    hipGraphExec_t x = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e == hipSuccess) { c->graphs[nsteps] = x; *out = x; }
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -158,7 +287,6 @@ af_status af_init(const af_config* cfg, void* hip_stream, af_ctx** out) {
     if (cfg->precision == AF_F32 && (!(cfg->bg[0] > 0.0) || !(cfg->bg[3] > 0.0))) return AF_ERR_ARG;
     af_ctx* c = new (std::nothrow) af_ctx();
     if (!c) return AF_ERR_ARG;
-    std::memset(c, 0, sizeof(*c));
     c->cfg = *cfg;
     c->stream = (hipStream_t)hip_stream;
     c->N = (size_t)cfg->nx * cfg->ny;
@@ -197,6 +325,7 @@ af_status af_init(const af_config* cfg, void* hip_stream, af_ctx** out) {
 
 void af_destroy(af_ctx* c) {
     if (!c) return;
+    if (c->cap) (void)hipStreamSynchronize(c->cap);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     if (c->state2) (void)hipFree(c->state2);
@@ -207,6 +336,13 @@ void af_destroy(af_ctx* c) {
     if (c->diag_out) (void)hipFree(c->diag_out);
     if (c->comp) (void)hipFree(c->comp);
     if (c->adj_scratch) (void)hipFree(c->adj_scratch);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (void* p : c->bbufs) (void)hipFree(p);
+    if (c->d_binst) (void)hipFree(c->d_binst);
+    if (c->d_work) (void)hipFree(c->d_work);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    for (int k = 0; k < 2; ++k)
+        if (c->bev[k]) (void)hipEventDestroy(c->bev[k]);
     for (int k = 0; k < 2; ++k)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     delete c;
@@ -214,6 +350,7 @@ void af_destroy(af_ctx* c) {
 
 af_status af_step_out(af_ctx* c, const af_state* in, af_state* out, double dt) {
     if (!c || !state_ok(in) || !state_ok(out) || !(dt > 0.0) || !std::isfinite(dt)) return AF_ERR_ARG;
+    if (c->nbatch) return AF_ERR_UNSUPPORTED;
     void *pi[16], *po[16];
     planes_of(in, pi);
     planes_of(out, po);
@@ -230,6 +367,7 @@ af_status af_step_out(af_ctx* c, const af_state* in, af_state* out, double dt) {
 
 af_status af_step(af_ctx* c, af_state* inout, double dt, int32_t nsteps) {
     if (!c || !state_ok(inout) || !(dt > 0.0) || !std::isfinite(dt) || nsteps < 1) return AF_ERR_ARG;
+    if (c->nbatch) return AF_ERR_UNSUPPORTED;
     void *a[16], *b[16];
     planes_of(inout, a);
     planes_of_buffer(c->state2, c->N, c->elem, b);
@@ -266,7 +404,7 @@ af_status af_read_status(af_ctx* c, af_status* status) {
 af_status af_step_adjoint(af_ctx* c, const af_state* primal_n, const af_state* cot_np1, af_state* cot_n,
                           double dt) {
     if (!c || !state_ok(primal_n) || !state_ok(cot_np1) || !state_ok(cot_n) || !(dt > 0.0)) return AF_ERR_ARG;
-    if (c->f32 || (c->cfg.flags & AF_SCHEME_RB)) return AF_ERR_UNSUPPORTED;
+    if (c->f32 || c->nbatch || (c->cfg.flags & AF_SCHEME_RB)) return AF_ERR_UNSUPPORTED;
     if (!c->adj_scratch) AF_HIP(hipMalloc(&c->adj_scratch, af::scratch_bytes_adjoint_f64(c->cfg.nx, c->cfg.ny)));
     af::StepArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -288,6 +426,7 @@ af_status af_step_adjoint(af_ctx* c, const af_state* primal_n, const af_state* c
 
 af_status af_diagnostics(af_ctx* c, const af_state* s, double dt, af_diag* out) {
     if (!c || !state_ok(s) || !out) return AF_ERR_ARG;
+    if (c->nbatch) return AF_ERR_UNSUPPORTED;
     void* p[16];
     planes_of(s, p);
     AF_HIP(af::launch_diag(p, c->f32, c->cfg.bg, c->cfg.nx, c->cfg.ny, c->cfg.h, c->cfg.gamma, c->partials,
@@ -312,6 +451,7 @@ af_status af_time_steps(af_ctx* c, const af_state* s, double dt, int32_t nsteps,
                         double* kernel_ms) {
     if (!c || !state_ok(s) || nsteps < 1 || nsteps > 4096 || !total_ms || !kernel_ms || !(dt > 0.0))
         return AF_ERR_ARG;
+    if (c->nbatch) return AF_ERR_UNSUPPORTED;
     if (!c->state3) AF_HIP(hipMalloc(&c->state3, 16 * c->N * c->elem));
     void *src[16], *a[16], *b[16];
     planes_of(s, src);
@@ -353,11 +493,150 @@ af_status af_time_steps(af_ctx* c, const af_state* s, double dt, int32_t nsteps,
     return AF_OK;
 }
 
+
+af_status af_init_batch(const af_config* cfgs, int32_t n, void* hip_stream, af_ctx** out) {
+    if (!cfgs || !out || n < 1 || n > 4096) return AF_ERR_ARG;
+    *out = nullptr;
+    for (int q = 0; q < n; ++q) {
+        const af_config& cf = cfgs[q];
+        if (cf.nx < 4 || cf.ny < 4 || !(cf.h > 0.0) || !(cf.gamma > 1.0) || !std::isfinite(cf.h)) return AF_ERR_ARG;
+        if (cf.precision != AF_F32) return AF_ERR_UNSUPPORTED;
+        if (!(cf.bg[0] > 0.0) || !(cf.bg[3] > 0.0)) return AF_ERR_ARG;
+        if (cf.flags & AF_SCHEME_RB) return AF_ERR_UNSUPPORTED;
+    }
+    af_ctx* c = new (std::nothrow) af_ctx();
+    if (!c) return AF_ERR_ARG;
+    c->cfg = cfgs[0];
+    c->stream = (hipStream_t)hip_stream;
+    c->f32 = true;
+    c->elem = sizeof(float);
+    c->nbatch = n;
+    c->bcfg.assign(cfgs, cfgs + n);
+    c->binst.resize(n);
+    c->btraj.assign(n, nullptr);
+    if (const char* v = std::getenv("AF_BATCH_TILE")) {
+        const int k = std::atoi(v);
+        if (k >= 0 && k < af::kNumBatchCfgs) c->force_cfg = k;
+    }
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&c->bev[k], hipEventDisableTiming);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->status, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->d_binst, n * sizeof(af::BatchInst));
+    for (int q = 0; q < n && e == hipSuccess; ++q) {
+        const af_config& cf = cfgs[q];
+        af::BatchInst& d = c->binst[q];
+        std::memset(&d, 0, sizeof(d));
+        d.nx = cf.nx;
+        d.ny = cf.ny;
+        d.pol = af::pert_pol_f32(cf.bg, cf.gamma);
+        const size_t N = (size_t)cf.nx * cf.ny;
+        void *b = nullptr, *cp = nullptr;
+        e = hipMalloc(&b, 16 * N * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(&cp, 4 * N * sizeof(float));
+        if (e == hipSuccess) e = hipMemsetAsync(cp, 0, 4 * N * sizeof(float), c->stream);
+        c->bbufs.push_back(b);
+        c->bbufs.push_back(cp);
+        for (int k = 0; k < 16; ++k) d.S[1][k] = (float*)b + (size_t)k * N;
+        d.comp = (float*)cp;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        g_last_hip = (int)e;
+        af_destroy(c);
+        return AF_ERR_HIP;
+    }
+    *out = c;
+    return AF_OK;
+}
+
+af_status af_step_batch(af_ctx* c, af_state* states, const double* dts, int32_t nsteps) {
+    if (!c || !states || !dts || nsteps < 1 || nsteps > 65536) return AF_ERR_ARG;
+    if (c->nbatch < 1) return AF_ERR_UNSUPPORTED;
+    for (int q = 0; q < c->nbatch; ++q) {
+        if (!state_ok(&states[q]) || !(dts[q] > 0.0) || !std::isfinite(dts[q])) return AF_ERR_ARG;
+    }
+    for (int q = 0; q < c->nbatch; ++q) {
+        af::BatchInst& d = c->binst[q];
+        void* p[16];
+        planes_of(&states[q], p);
+        for (int k = 0; k < 16; ++k) d.S[0][k] = (float*)p[k];
+        d.lam1 = (float)(dts[q] / c->bcfg[q].h);
+        d.lam0 = (float)(0.5 * dts[q] / c->bcfg[q].h);
+        if (c->btraj[q] != p[0]) {   // a new trajectory: fresh compensation
+            AF_HIP(hipMemsetAsync(d.comp, 0, 4 * (size_t)d.nx * d.ny * sizeof(float), c->stream));
+            c->btraj[q] = p[0];
+        }
+    }
+    if (c->tune_cfg < 0) {
+        if (c->force_cfg >= 0) {
+            AF_HIP(batch_build_work(c, c->force_cfg));
+            c->tune_cfg = c->force_cfg;
+        } else {
+            AF_HIP(batch_tune(c));
+        }
+    }
+    AF_HIP(batch_upload(c, c->stream));
+    hipGraphExec_t gx = nullptr;
+    AF_HIP(batch_graph(c, nsteps, &gx));
+    // order the replay after the caller's stream and make the caller's stream wait for it
+    AF_HIP(hipEventRecord(c->bev[0], c->stream));
+    AF_HIP(hipStreamWaitEvent(c->cap, c->bev[0], 0));
+    AF_HIP(hipGraphLaunch(gx, c->cap));
+    AF_HIP(hipEventRecord(c->bev[1], c->cap));
+    AF_HIP(hipStreamWaitEvent(c->stream, c->bev[1], 0));
+    if (c->cfg.flags & AF_CHECK) {
+        unsigned bits;
+        af_status st = read_status(c, &bits);
+        if (st != AF_OK) return st;
+        return status_from_bits(bits);
+    }
+    return AF_OK;
+}
+
+int32_t af_batch_info(af_ctx* c, char* buf, int32_t buflen) {
+    if (!c || c->nbatch < 1 || !buf || buflen < 1) return -1;
+    std::string s = "{\"instances\": " + std::to_string(c->nbatch) + ", \"work_items\": " + std::to_string(c->nwork) +
+                    ", \"grid\": " + std::to_string(c->grid) + ", \"chosen\": ";
+    if (c->tune_cfg >= 0) {
+        const af::BatchTileCfg t = af::kBatchCfgs[c->tune_cfg];
+        s += "[" + std::to_string(t.tx) + ", " + std::to_string(t.ty) + ", " + std::to_string(t.nt) + "]";
+    } else {
+        s += "null";
+    }
+    s += ", \"candidates\": [";
+    for (int k = 0; k < af::kNumBatchCfgs; ++k) {
+        const af::BatchTileCfg t = af::kBatchCfgs[k];
+        char tmp[160];
+        std::snprintf(tmp, sizeof(tmp), "%s{\"tile\": [%d, %d, %d], \"ms_per_step\": %.6f}", k ? ", " : "", t.tx, t.ty,
+                      t.nt, c->tune_ms[k]);
+        s += tmp;
+    }
+    s += "]}";
+    const int32_t n = (int32_t)s.size();
+    std::strncpy(buf, s.c_str(), (size_t)buflen);
+    buf[buflen - 1] = '\0';
+    return n;
+}
+
 const char* af_dominant_kernel(af_ctx* c) {
-    if (c && c->f32) return "af::k_fused<float, PolPert<float>, 32, 8, 512, 0, true>";
+    if (c && c->nbatch) {
+        if (c->tune_cfg < 0) return "af::k_fused_batch (tile not chosen yet)";
+        const af::BatchTileCfg t = af::kBatchCfgs[c->tune_cfg];
+        c->kname = "af::k_fused_batch<" + std::to_string(t.tx) + ", " + std::to_string(t.ty) + ", " +
+                   std::to_string(t.nt) + ">";
+        return c->kname.c_str();
+    }
+    const bool rb = c && (c->cfg.flags & AF_SCHEME_RB);
+    if (c && c->f32)
+        return rb ? "af::k_fused<float, af::PolPert<float>, 32, 8, 512, 1, true>"
+                  : "af::k_fused<float, af::PolPert<float>, 32, 8, 512, 0, true>";
     if (c && c->variant == 1) return "af_step multi-kernel sequence";
-    if (c && c->variant == 2) return "af::k_points_update<32, 8, 512, 0>";
-    return "af::k_fused<32, 8, 512, 0>";
+    if (c && c->variant == 2) return rb ? "af::k_points_update<32, 8, 512, 1>" : "af::k_points_update<32, 8, 512, 0>";
+    return rb ? "af::k_fused<double, af::PolAbs<double>, 32, 8, 512, 1, false>"
+              : "af::k_fused<double, af::PolAbs<double>, 32, 8, 512, 0, false>";
 }
 
 }  // extern "C"

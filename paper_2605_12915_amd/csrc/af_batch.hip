@@ -1,0 +1,116 @@
+// Batching form: many FP32 grids of uneven sizes stepped by ONE persistent launch per
+// step.  The work list holds every (instance, tile) pair of the batch; a grid of
+// (CUs x resident workgroups) persistent workgroups walks contiguous chunks of it
+// (chunks numbered XCD-aware, so a workgroup's neighbours in the list run on the
+// same XCD), calling the same fused tile computation as the single-grid kernel,
+// with each instance's own size, background, dt and buffers read from a device
+// descriptor array.  af_step_batch captures nsteps launches (alternating the ping-
+// pong direction) in a hipGraph and replays it.  The tile shape comes from the
+// autotuner (af_api.hip), which times every instantiation below on the batch.
+#include <hip/hip_runtime.h>
+
+#include "af_batch.h"
+#include "af_fused.h"
+
+namespace af {
+
+// One work item.  Kept out of line on purpose: inlined into the persistent loop below,
+// the compiler keeps the tile body's constants live across iterations and spills;
+// as a call, the body gets the single-grid kernel's register allocation and the
+// loop pays only the callee-saved registers of one call per tile.
+template <int TX, int TY, int NT>
+__device__ __noinline__ unsigned batch_tile(const BatchInst* __restrict__ inst, int2 it, int parity) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    auto& L = *reinterpret_cast<FusedTile<float, TX, TY>*>(smem);
+    const BatchInst& d = inst[it.x];
+    const PlaneView in{{d.S[parity]}}, out{{d.S[parity ^ 1]}};
+    unsigned st = 0;
+    fused_tile<float, PolPert<float>, TX, TY, NT, 0, true>(L, in, out, d.comp, d.nx, d.ny,
+                                                           (it.y % d.tiles_x) * TX, (it.y / d.tiles_x) * TY,
+                                                           d.pol, d.lam0, d.lam1, st);
+    return st;
+}
+
+template <int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_fused_batch(const BatchInst* __restrict__ inst,
+                                                    const int2* __restrict__ work, int nwork, int parity,
+                                                    unsigned* status) {
+    const int G = gridDim.x;
+    // XCD-aware chunk number: consecutive chunks go to workgroups on the same XCD
+    int b;
+    {
+        const int xcd = blockIdx.x & 7;
+        int base = 0;
+        for (int x = 0; x < xcd; ++x) base += (G - x + 7) >> 3;
+        b = base + (blockIdx.x >> 3);
+    }
+    const int chunk = (nwork + G - 1) / G;
+    const int w0 = b * chunk, w1 = min(nwork, w0 + chunk);
+    unsigned st = 0;
+    for (int w = w0; w < w1; ++w) {
+        st |= batch_tile<TX, TY, NT>(inst, work[w], parity);
+        __syncthreads();          // the next tile reuses the LDS
+    }
+    if (st) atomicOr(status, st);
+}
+
+// partner -> caller's buffer for every instance (the odd-step tail of a captured sequence).
+__global__ void __launch_bounds__(256) k_batch_copy(const BatchInst* inst, int n) {
+    for (int q = 0; q < n; ++q) {
+        const BatchInst& d = inst[q];
+        const size_t N = (size_t)d.nx * d.ny;
+        for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < 16 * N; e += (size_t)gridDim.x * blockDim.x)
+            d.S[0][e / N][e % N] = d.S[1][e / N][e % N];
+    }
+}
+
+template <int TX, int TY, int NT>
+static hipError_t launch_cfg(const BatchInst* inst, const int2* work, int nwork, int parity, unsigned* status,
+                             int grid, hipStream_t s) {
+    const size_t lds = sizeof(FusedTile<float, TX, TY>);
+    hipLaunchKernelGGL((k_fused_batch<TX, TY, NT>), dim3(grid), dim3(NT), lds, s, inst, work, nwork, parity, status);
+    return hipGetLastError();
+}
+
+template <int TX, int TY, int NT>
+static hipError_t occupancy_cfg(int* blocks_per_cu) {
+    const size_t lds = sizeof(FusedTile<float, TX, TY>);
+    hipError_t e = hipFuncSetAttribute((const void*)k_fused_batch<TX, TY, NT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused_batch<TX, TY, NT>, NT, lds);
+}
+
+const BatchTileCfg kBatchCfgs[kNumBatchCfgs] = {
+    {32, 8, 512}, {32, 8, 256}, {32, 16, 512}, {32, 16, 256}, {64, 8, 512}, {16, 16, 256},
+};
+
+hipError_t batch_occupancy(int cfg, int* blocks_per_cu) {
+    switch (cfg) {
+        case 0: return occupancy_cfg<32, 8, 512>(blocks_per_cu);
+        case 1: return occupancy_cfg<32, 8, 256>(blocks_per_cu);
+        case 2: return occupancy_cfg<32, 16, 512>(blocks_per_cu);
+        case 3: return occupancy_cfg<32, 16, 256>(blocks_per_cu);
+        case 4: return occupancy_cfg<64, 8, 512>(blocks_per_cu);
+        default: return occupancy_cfg<16, 16, 256>(blocks_per_cu);
+    }
+}
+
+hipError_t launch_batch(int cfg, const BatchInst* inst, const int2* work, int nwork, int parity, unsigned* status,
+                        int grid, hipStream_t s) {
+    switch (cfg) {
+        case 0: return launch_cfg<32, 8, 512>(inst, work, nwork, parity, status, grid, s);
+        case 1: return launch_cfg<32, 8, 256>(inst, work, nwork, parity, status, grid, s);
+        case 2: return launch_cfg<32, 16, 512>(inst, work, nwork, parity, status, grid, s);
+        case 3: return launch_cfg<32, 16, 256>(inst, work, nwork, parity, status, grid, s);
+        case 4: return launch_cfg<64, 8, 512>(inst, work, nwork, parity, status, grid, s);
+        default: return launch_cfg<16, 16, 256>(inst, work, nwork, parity, status, grid, s);
+    }
+}
+
+hipError_t launch_batch_copy(const BatchInst* inst, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_copy, dim3(1024), dim3(256), 0, s, inst, n);
+    return hipGetLastError();
+}
+
+}  // namespace af

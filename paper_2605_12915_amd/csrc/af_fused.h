@@ -1,0 +1,292 @@
+// The fused, LDS-tiled RB-TAI tile computation (device code shared by the
+// single-grid kernel in af_fused.hip and the batched persistent kernel in
+// af_batch.hip).  See af_fused.hip for the phase structure.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "af_internal.h"
+#include "af_kernels.h"
+
+namespace af {
+
+template <class T, int TX, int TY>
+struct FusedTile {
+    static constexpr int PX = TX + 5, PY = TY + 5;   // primitives: cells [-2, T+3)
+    static constexpr int CX = TX + 4, CY = TY + 4;   // centres:    cells [-2, T+2)
+    static constexpr int DX = TX + 3, DY = TY + 3;   // increments: node-cells [-1, T+2)
+    static constexpr int VX = TX + 1, VY = TY + 1;   // flux nodes: node-cells [0, T]
+    T P[12][PY][PX];
+    T C[4][CY][CX];
+    union {
+        T D[2][12][DY][DX];                          // [tau][fam*3 + var]
+        struct {
+            T FV[8][VY][VX];                         // V nodes: F~ (0..3), G~ (4..7)
+            T FE[4][TY][VX];                         // Ev nodes: F~
+            T GE[4][VY][TX];                         // Eh nodes: G~
+        } F;
+    };
+};
+
+template <class T, int TX, int TY>
+struct LdsAcc {
+    const FusedTile<T, TX, TY>* t;
+    __device__ __forceinline__ Prim<T> node(int fam, int x, int y) const {
+        if (fam == F_C) return {t->C[0][y + 2][x + 2], t->C[1][y + 2][x + 2], t->C[2][y + 2][x + 2], t->C[3][y + 2][x + 2]};
+        const int b = 4 * fam;
+        return {t->P[b][y + 2][x + 2], t->P[b + 1][y + 2][x + 2], t->P[b + 2][y + 2][x + 2], t->P[b + 3][y + 2][x + 2]};
+    }
+};
+
+template <class T, int TX, int TY>
+struct LdsInc {
+    const FusedTile<T, TX, TY>* t;
+    int tau;
+    __device__ __forceinline__ T inc(int fam, int x, int y, int var) const {
+        return t->D[tau][fam * 3 + var][y + 1][x + 1];
+    }
+};
+
+template <int B, class SP, class T>
+__device__ __forceinline__ void store_prim(const SP& o, size_t g, const Prim<T>& w) {
+    o.p[B][g] = w.r;
+    o.p[B + 1][g] = w.u;
+    o.p[B + 2][g] = w.v;
+    o.p[B + 3][g] = w.p;
+}
+
+__device__ __forceinline__ int wrap_any(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// One tile: cells [i0, i0+TX) x [j0, j0+TY) of one grid.  Called by the single-grid
+// kernel (one tile per workgroup) and by the batched persistent kernel (a list of
+// tiles of many grids per workgroup).  The arithmetic of every node does not depend
+// on the tile shape or on which kernel calls it; compiled with -ffp-contract=on in
+// both, the FP32 kernels therefore agree bit for bit.
+// kFamilyFence: in FP64, phase 2 computes the four families' increments one after
+// the other with a scheduling fence between them; interleaving them (the compiler's
+// choice without it) needs more than the 256 registers a wave can hold at this
+// workgroup size and spills.  In FP32 the interleaving fits and is faster.
+//
+// SP: any type with a member p such that p[k] is plane k's pointer (StatePtrs, or a
+// view of a descriptor in global memory whose pointers are loaded where used).
+template <class T, class Pol, int TX, int TY, int NT, int SCHEME, bool KAHAN, class SP>
+__device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in, const SP& out,
+                                           T* comp, int nx, int ny, int i0, int j0, const Pol pol, T lam0, T lam1,
+                                           unsigned& st) {
+    using Tile = FusedTile<T, TX, TY>;
+    const int tid = threadIdx.x;
+
+    // ---- phase 0: primitive node values of cells [-2, T+3)^2 ------------------------
+    for (int e = tid; e < Tile::PX * Tile::PY; e += NT) {
+        const int x = e % Tile::PX, y = e / Tile::PX;
+        const size_t g = (size_t)wrap_any(j0 + y - 2, ny) * nx + wrap_any(i0 + x - 2, nx);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) L.P[k][y][x] = in.p[4 + k][g];
+    }
+    __syncthreads();
+
+    // ---- phase 1: recovered centres of cells [-2, T+2)^2 ------------------------------
+    {
+        LdsAcc<T, TX, TY> A{&L};
+        for (int e = tid; e < Tile::CX * Tile::CY; e += NT) {
+            const int x = e % Tile::CX - 2, y = e / Tile::CX - 2;
+            const size_t g = (size_t)wrap_any(j0 + y, ny) * nx + wrap_any(i0 + x, nx);
+            const T Ub[4] = {in.p[0][g], in.p[1][g], in.p[2][g], in.p[3][g]};
+            Prim<T> w = pol.centre(Ub, A.node(F_V, x, y), A.node(F_V, x + 1, y), A.node(F_V, x, y + 1),
+                                   A.node(F_V, x + 1, y + 1), A.node(F_EH, x, y), A.node(F_EH, x, y + 1),
+                                   A.node(F_EV, x, y), A.node(F_EV, x + 1, y));
+            if (!(pol.rho(w.r) > T(0)) || !(pol.pr(w.p) > T(0))) st |= SB_NONPHYS;
+            L.C[0][y + 2][x + 2] = w.r;
+            L.C[1][y + 2][x + 2] = w.u;
+            L.C[2][y + 2][x + 2] = w.v;
+            L.C[3][y + 2][x + 2] = w.p;
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 2: increments at node-cells [-1, T+2)^2, both durations ---------------
+    {
+        LdsAcc<T, TX, TY> A{&L};
+        for (int e = tid; e < Tile::DX * Tile::DY; e += NT) {
+            const int x = e % Tile::DX - 1, y = e / Tile::DX - 1;
+            T d[2][3];
+            node_increments<F_V>(A, x, y, pol, lam0, lam1, d, st);
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int v = 0; v < 3; ++v) L.D[t][0 * 3 + v][y + 1][x + 1] = d[t][v];
+            if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);   // see kFamilyFence
+            node_increments<F_EV>(A, x, y, pol, lam0, lam1, d, st);
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int v = 0; v < 3; ++v) L.D[t][1 * 3 + v][y + 1][x + 1] = d[t][v];
+            if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);   // see kFamilyFence
+            node_increments<F_EH>(A, x, y, pol, lam0, lam1, d, st);
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int v = 0; v < 3; ++v) L.D[t][2 * 3 + v][y + 1][x + 1] = d[t][v];
+            if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);   // see kFamilyFence
+            node_increments<F_C>(A, x, y, pol, lam0, lam1, d, st);
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int v = 0; v < 3; ++v) L.D[t][3 * 3 + v][y + 1][x + 1] = d[t][v];
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 3: point updates of targets in node-cells [0, T] ----------------------
+    constexpr int NV_ = Tile::VX * Tile::VY, NE_ = Tile::VX * TY, NH_ = TX * Tile::VY;
+    constexpr int NITEMS = NV_ + NE_ + NH_;
+    constexpr int ROUNDS = (NITEMS + NT - 1) / NT;
+    T fres[ROUNDS][8];
+    {
+        LdsAcc<T, TX, TY> A{&L};
+        LdsInc<T, TX, TY> D0{&L, 0}, D1{&L, 1};
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            const int e = r * NT + tid;
+            if (e >= NITEMS) continue;
+            int fam, x, y;
+            if (e < NV_) { fam = F_V; x = e % Tile::VX; y = e / Tile::VX; }
+            else if (e < NV_ + NE_) { fam = F_EV; x = (e - NV_) % Tile::VX; y = (e - NV_) / Tile::VX; }
+            else { fam = F_EH; x = (e - NV_ - NE_) % TX; y = (e - NV_ - NE_) / TX; }
+            Prim<T> w0, wh, w1;
+            // new point values of owned nodes (plane indices kept static: a dynamic
+            // index into the pointer set would put it in private memory)
+            const bool own = x < TX && y < TY && i0 + x < nx && j0 + y < ny;
+            const size_t g = own ? (size_t)(j0 + y) * nx + (i0 + x) : 0;
+            if (fam == F_V) {
+                w0 = A.node(F_V, x, y);
+                point_update_pair<F_V, SCHEME>(A, D0, D1, x, y, pol, lam0, lam1, st, wh, w1);
+                if (own) store_prim<4>(out, g, w1);
+            } else if (fam == F_EV) {
+                w0 = A.node(F_EV, x, y);
+                point_update_pair<F_EV, SCHEME>(A, D0, D1, x, y, pol, lam0, lam1, st, wh, w1);
+                if (own) store_prim<8>(out, g, w1);
+            } else {
+                w0 = A.node(F_EH, x, y);
+                point_update_pair<F_EH, SCHEME>(A, D0, D1, x, y, pol, lam0, lam1, st, wh, w1);
+                if (own) store_prim<12>(out, g, w1);
+            }
+            T F0[4], Fh[4], F1[4];
+            if (fam != F_EH) {
+                pol.fx(w0, F0); pol.fx(wh, Fh); pol.fx(w1, F1);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) fres[r][k] = (F0[k] + T(4) * Fh[k] + F1[k]) * T(1.0 / 6.0);
+            }
+            if (fam != F_EV) {
+                pol.fy(w0, F0); pol.fy(wh, Fh); pol.fy(w1, F1);
+                const int o = (fam == F_V) ? 4 : 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) fres[r][o + k] = (F0[k] + T(4) * Fh[k] + F1[k]) * T(1.0 / 6.0);
+            }
+        }
+    }
+    __syncthreads();     // every read of D is done: the flux arrays may alias it
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int e = r * NT + tid;
+        if (e >= NITEMS) continue;
+        if (e < NV_) {
+            const int x = e % Tile::VX, y = e / Tile::VX;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) L.F.FV[k][y][x] = fres[r][k];
+        } else if (e < NV_ + NE_) {
+            const int x = (e - NV_) % Tile::VX, y = (e - NV_) / Tile::VX;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) L.F.FE[k][y][x] = fres[r][k];
+        } else {
+            const int x = (e - NV_ - NE_) % TX, y = (e - NV_ - NE_) / TX;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) L.F.GE[k][y][x] = fres[r][k];
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 4: average update of the owned cells -----------------------------------
+    for (int e = tid; e < TX * TY; e += NT) {
+        const int x = e % TX, y = e / TX;
+        if (i0 + x >= nx || j0 + y >= ny) continue;
+        const size_t g = (size_t)(j0 + y) * nx + (i0 + x);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const T Fl = (L.F.FV[k][y][x] + T(4) * L.F.FE[k][y][x] + L.F.FV[k][y + 1][x]) * T(1.0 / 6.0);
+            const T Fr = (L.F.FV[k][y][x + 1] + T(4) * L.F.FE[k][y][x + 1] + L.F.FV[k][y + 1][x + 1]) * T(1.0 / 6.0);
+            const T Gb = (L.F.FV[4 + k][y][x] + T(4) * L.F.GE[k][y][x] + L.F.FV[4 + k][y][x + 1]) * T(1.0 / 6.0);
+            const T Gt = (L.F.FV[4 + k][y + 1][x] + T(4) * L.F.GE[k][y + 1][x] + L.F.FV[4 + k][y + 1][x + 1]) * T(1.0 / 6.0);
+            const T delta = -lam1 * ((Fr - Fl) + (Gt - Gb));
+            if constexpr (KAHAN) {
+                // compensated sum: the low-order part lost when adding delta is carried
+                // in comp and fed back into the next step's increment
+                const size_t N = (size_t)nx * ny;
+                auto* __restrict__ cg = (__attribute__((address_space(1))) T*)comp;
+                const T old = in.p[k][g];
+                const T y_ = delta - cg[k * N + g];
+                const T t_ = old + y_;
+                cg[k * N + g] = (t_ - old) - y_;
+                out.p[k][g] = t_;
+            } else {
+                out.p[k][g] = in.p[k][g] + delta;
+            }
+        }
+    }
+}
+
+// ---- single-grid kernel: one tile per workgroup --------------------------------------
+template <class T, class Pol, int TX, int TY, int NT, int SCHEME, bool KAHAN>
+__global__ void __launch_bounds__(NT) k_fused(StatePtrs<T> in, StatePtrs<T> out, T* comp, int nx, int ny,
+                                              int tiles_x, int ntiles, Pol pol, T lam0, T lam1, unsigned* status) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    auto& L = *reinterpret_cast<FusedTile<T, TX, TY>*>(smem);
+    // XCD-aware numbering: hardware dispatches consecutive workgroups round-robin over
+    // the 8 XCDs; give each XCD a contiguous run of tiles.
+    int tile;
+    {
+        const int b = blockIdx.x, xcd = b & 7;
+        int base = 0;
+        for (int x = 0; x < xcd; ++x) base += (ntiles - x + 7) >> 3;
+        tile = base + (b >> 3);
+    }
+    unsigned st = 0;
+    fused_tile<T, Pol, TX, TY, NT, SCHEME, KAHAN>(L, in, out, comp, nx, ny, (tile % tiles_x) * TX,
+                                                  (tile / tiles_x) * TY, pol, lam0, lam1, st);
+    if (st) atomicOr(status, st);
+}
+
+
+template <class T, class Pol, int TX, int TY, int NT, bool KAHAN>
+hipError_t launch_fused(const StepArgs& a, const Pol& pol) {
+    StatePtrs<T> in, out;
+    for (int k = 0; k < 16; ++k) { in.p[k] = (T*)a.in[k]; out.p[k] = (T*)a.out[k]; }
+    const int tiles_x = (a.nx + TX - 1) / TX, tiles_y = (a.ny + TY - 1) / TY;
+    const int ntiles = tiles_x * tiles_y;
+    const T lam1 = T(a.dt / a.h), lam0 = T(0.5 * a.dt / a.h);
+    const size_t lds = sizeof(FusedTile<T, TX, TY>);
+    T* comp = (T*)a.comp;
+    if (a.ev_begin) (void)hipEventRecord(a.ev_begin, a.stream);
+    if (a.scheme == 0)
+        hipLaunchKernelGGL((k_fused<T, Pol, TX, TY, NT, 0, KAHAN>), dim3(ntiles), dim3(NT), lds, a.stream, in, out, comp,
+                           a.nx, a.ny, tiles_x, ntiles, pol, lam0, lam1, a.status);
+    else
+        hipLaunchKernelGGL((k_fused<T, Pol, TX, TY, NT, 1, KAHAN>), dim3(ntiles), dim3(NT), lds, a.stream, in, out, comp,
+                           a.nx, a.ny, tiles_x, ntiles, pol, lam0, lam1, a.status);
+    if (a.ev_end) (void)hipEventRecord(a.ev_end, a.stream);
+    return hipGetLastError();
+}
+
+template <class T, class Pol, int TX, int TY, int NT, bool KAHAN>
+hipError_t prepare_fused() {
+    const size_t lds = sizeof(FusedTile<T, TX, TY>);
+    hipError_t e = hipFuncSetAttribute((const void*)k_fused<T, Pol, TX, TY, NT, 0, KAHAN>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_fused<T, Pol, TX, TY, NT, 1, KAHAN>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+}  // namespace af

@@ -181,7 +181,7 @@ AF_HD void point_update_pair(const A& acc, const D& d0, const D& d1, int i, int 
         cx = (int)fcx;
         cy = (int)fcy;
         const int ci = i + cx, cj = j + cy;
-        T fr[3][3], fu[3][3], fv[3][3], fp[3][3], g[2][3][3][3];
+        T fr[3][3], fu[3][3], fv[3][3], fp[3][3];
         {
             Prim<T> n[3][3];
             cell_nodes<T>(acc, ci, cj, n);
@@ -191,20 +191,6 @@ AF_HD void point_update_pair(const A& acc, const D& d0, const D& d1, int i, int 
                 for (int b = 0; b < 3; ++b) {
                     fr[a][b] = n[a][b].r; fu[a][b] = n[a][b].u; fv[a][b] = n[a][b].v; fp[a][b] = n[a][b].p;
                 }
-        }
-        if constexpr (SCHEME == 0) {
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const D& dd = t ? d1 : d0;
-#pragma unroll
-                for (int var = 0; var < 3; ++var) {
-                    g[t][var][0][0] = dd.inc(F_V, ci, cj, var);      g[t][var][1][0] = dd.inc(F_EH, ci, cj, var);
-                    g[t][var][2][0] = dd.inc(F_V, ci + 1, cj, var);  g[t][var][0][1] = dd.inc(F_EV, ci, cj, var);
-                    g[t][var][1][1] = dd.inc(F_C, ci, cj, var);      g[t][var][2][1] = dd.inc(F_EV, ci + 1, cj, var);
-                    g[t][var][0][2] = dd.inc(F_V, ci, cj + 1, var);  g[t][var][1][2] = dd.inc(F_EH, ci, cj + 1, var);
-                    g[t][var][2][2] = dd.inc(F_V, ci + 1, cj + 1, var);
-                }
-            }
         }
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
@@ -227,9 +213,21 @@ AF_HD void point_update_pair(const A& acc, const D& d0, const D& d1, int i, int 
             Prim<T> Wf{q2(xm, xp, ym, yp, fr), q2(xm, xp, ym, yp, fu), q2(xm, xp, ym, yp, fv), q2(xm, xp, ym, yp, fp)};
             T du, dv, dp, rho_over_c2;
             if constexpr (SCHEME == 0) {
-                du = q2(xm, xp, ym, yp, g[t][0]);
-                dv = q2(xm, xp, ym, yp, g[t][1]);
-                dp = q2(xm, xp, ym, yp, g[t][2]);
+                // increments of the candidate cell's nine nodes for this duration,
+                // gathered per duration to bound the live set
+                const D& dd = t ? d1 : d0;
+                T g[3][3][3];
+#pragma unroll
+                for (int var = 0; var < 3; ++var) {
+                    g[var][0][0] = dd.inc(F_V, ci, cj, var);      g[var][1][0] = dd.inc(F_EH, ci, cj, var);
+                    g[var][2][0] = dd.inc(F_V, ci + 1, cj, var);  g[var][0][1] = dd.inc(F_EV, ci, cj, var);
+                    g[var][1][1] = dd.inc(F_C, ci, cj, var);      g[var][2][1] = dd.inc(F_EV, ci + 1, cj, var);
+                    g[var][0][2] = dd.inc(F_V, ci, cj + 1, var);  g[var][1][2] = dd.inc(F_EH, ci, cj + 1, var);
+                    g[var][2][2] = dd.inc(F_V, ci + 1, cj + 1, var);
+                }
+                du = q2(xm, xp, ym, yp, g[0]);
+                dv = q2(xm, xp, ym, yp, g[1]);
+                dp = q2(xm, xp, ym, yp, g[2]);
                 rho_over_c2 = pol.rho(Wf.r) / (pol.gamma * pol.pr(Wf.p));
             } else {
                 const D& dd = t ? d1 : d0;

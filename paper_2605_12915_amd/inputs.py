@@ -18,6 +18,8 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from typing import Callable, Tuple
 
 import numpy as np
@@ -64,16 +66,25 @@ def _gl(n: int):
     return 0.5 * (g + 1.0), 0.5 * w          # nodes in [0,1], weights sum to 1
 
 
+def _workers() -> int:
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return max(1, min(16, os.cpu_count() or 1))
+
+
 def make_state(prim: PrimFn, nx: int, ny: int, x0: float, y0: float, h: float,
                gamma: float, ngl: int = 5, chunk_rows: int = 64) -> np.ndarray:
     """Cell averages by ngl x ngl Gauss-Legendre quadrature of U(W(x,y)); point
-    values sampled from W(x,y)."""
+    values sampled from W(x,y).  Row chunks are independent and evaluated by a
+    thread pool (numpy releases the GIL); the result does not depend on it."""
     s = np.empty((NPLANES, ny, nx), dtype=np.float64)
     gx, gw = _gl(ngl)
     xi = x0 + h * np.arange(nx, dtype=np.float64)
     yj = y0 + h * np.arange(ny, dtype=np.float64)
     xq = (xi[:, None] + h * gx[None, :]).reshape(-1)
-    for j0 in range(0, ny, chunk_rows):
+
+    def averages(j0):
         j1 = min(ny, j0 + chunk_rows)
         yq = (yj[j0:j1, None] + h * gx[None, :]).reshape(-1)
         W = prim(xq, yq)
@@ -81,12 +92,24 @@ def make_state(prim: PrimFn, nx: int, ny: int, x0: float, y0: float, h: float,
         for k in range(4):
             a = U[k].reshape(j1 - j0, ngl, nx, ngl)
             s[AVG + k, j0:j1] = np.einsum("ajbk,j,k->ab", a, gw, gw, optimize=True)
-    for base, dx, dy in ((V, 0.0, 0.0), (EV, 0.0, 0.5), (EH, 0.5, 0.0)):
-        for j0 in range(0, ny, chunk_rows * 8):
-            j1 = min(ny, j0 + chunk_rows * 8)
+
+    def points(j0):
+        j1 = min(ny, j0 + chunk_rows)
+        for base, dx, dy in ((V, 0.0, 0.0), (EV, 0.0, 0.5), (EH, 0.5, 0.0)):
             W = prim(xi + dx * h, yj[j0:j1] + dy * h)
             for k in range(4):
                 s[base + k, j0:j1] = W[k]
+
+    starts = list(range(0, ny, chunk_rows))
+    nw = _workers()
+    if nw > 1 and len(starts) > 1:
+        with ThreadPoolExecutor(max_workers=nw) as ex:
+            list(ex.map(averages, starts))
+            list(ex.map(points, starts))
+    else:
+        for j0 in starts:
+            averages(j0)
+            points(j0)
     return s
 
 

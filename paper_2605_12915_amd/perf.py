@@ -31,7 +31,8 @@ ROOT = os.path.dirname(HERE)
 
 # Sources whose change invalidates a stored counter measurement of a kernel.
 KERNEL_SOURCES = {
-    "af::k_fused<32, 8, 512, 0>": ["af_fused.hip", "af_kernels.h", "af_device.h", "af_blocks.h"],
+    "af::k_fused<double, af::PolAbs<double>, 32, 8, 512, 0, false>":
+        ["af_fused.hip", "af_fused.h", "af_kernels.h", "af_device.h", "af_blocks.h", "af_internal.h"],
 }
 
 

@@ -120,6 +120,80 @@ class Stepper:
         return _lib.lib().af_dominant_kernel(self._ctx).decode()
 
 
+class Batch:
+    """Batching form: many FP32 perturbation grids (uneven sizes, each with its own h,
+    gamma, background and dt) stepped together, one persistent launch per step, the
+    nsteps launches replayed from a hipGraph (af_init_batch / af_step_batch)."""
+
+    def __init__(self, grids: Sequence[dict], check_errors: bool = False,
+                 stream: Optional[torch.cuda.Stream] = None, device: Optional[torch.device] = None):
+        """grids: one dict per instance with keys nx, ny, h and optional gamma (1.4),
+        bg ((1, 0, 0, 1)), x0, y0."""
+        L = _lib.lib()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        n = len(grids)
+        cfgs = (AfConfig * n)()
+        for q, g in enumerate(grids):
+            c = cfgs[q]
+            c.nx, c.ny, c.h = int(g["nx"]), int(g["ny"]), float(g["h"])
+            c.gamma = float(g.get("gamma", 1.4))
+            c.x0, c.y0 = float(g.get("x0", 0.0)), float(g.get("y0", 0.0))
+            c.precision = AF_F32
+            bg = g.get("bg", (1.0, 0.0, 0.0, 1.0))
+            for k in range(4):
+                c.bg[k] = float(bg[k])
+            c.flags = AF_CHECK if check_errors else 0
+        self.cfgs = cfgs
+        self.n = n
+        self._ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(L.af_init_batch(cfgs, n, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._ctx)),
+                  "af_init_batch")
+
+    def close(self):
+        if self._ctx and self._ctx.value:
+            _lib.lib().af_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, states: Sequence[torch.Tensor], dts: Sequence[float], nsteps: int = 1):
+        """Advance every states[q] (float32 (16, ny_q, nx_q) perturbation tensors) in place."""
+        if len(states) != self.n or len(dts) != self.n:
+            raise ValueError(f"expected {self.n} states and dts")
+        arr = (AfState * self.n)()
+        for q, t in enumerate(states):
+            c = self.cfgs[q]
+            if t.dtype != torch.float32 or tuple(t.shape) != (16, c.ny, c.nx) or t.device != self.device:
+                raise ValueError(f"instance {q}: expected a (16, {c.ny}, {c.nx}) float32 tensor on {self.device}")
+            arr[q] = state_struct(t)
+        d = (ctypes.c_double * self.n)(*[float(x) for x in dts])
+        check(_lib.lib().af_step_batch(self._ctx, arr, d, int(nsteps)), "af_step_batch")
+        return states
+
+    def read_status(self) -> int:
+        """Read and clear the batch's device status flag (synchronises the stream)."""
+        st = ctypes.c_int32()
+        check(_lib.lib().af_read_status(self._ctx, ctypes.byref(st)), "af_read_status")
+        return st.value
+
+    def info(self) -> dict:
+        import json
+        buf = ctypes.create_string_buffer(8192)
+        n = _lib.lib().af_batch_info(self._ctx, buf, len(buf))
+        if n < 0:
+            raise RuntimeError("af_batch_info failed")
+        return json.loads(buf.value.decode())
+
+    def dominant_kernel(self) -> str:
+        return _lib.lib().af_dominant_kernel(self._ctx).decode()
+
+
 def background_cons(bg, gamma):
     r, u, v, p = (float(x) for x in bg)
     return (r, r * u, r * v, p / (gamma - 1.0) + 0.5 * r * (u * u + v * v))

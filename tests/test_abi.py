@@ -53,3 +53,26 @@ def test_status_strings(L):
     for code in range(7):
         assert L.af_status_string(code)
     assert b"CFL" in L.af_status_string(_lib.AF_ERR_ACOUSTIC_CFL)
+
+
+def test_bad_batch_config_rejected_on_host(L):
+    from paper_2605_12915_amd import _lib
+    cfgs = (_lib.AfConfig * 2)()
+    for c in cfgs:
+        c.nx, c.ny, c.h, c.gamma, c.precision = 8, 8, 0.1, 1.4, _lib.AF_F32
+        c.bg[0], c.bg[3] = 1.0, 1.0
+    ctx = ctypes.c_void_p()
+    assert L.af_init_batch(cfgs, 0, None, ctypes.byref(ctx)) == _lib.AF_ERR_ARG
+    assert L.af_init_batch(None, 2, None, ctypes.byref(ctx)) == _lib.AF_ERR_ARG
+    cfgs[1].precision = _lib.AF_F64
+    assert L.af_init_batch(cfgs, 2, None, ctypes.byref(ctx)) == _lib.AF_ERR_UNSUPPORTED
+    cfgs[1].precision = _lib.AF_F32
+    cfgs[1].flags = _lib.AF_SCHEME_RB
+    assert L.af_init_batch(cfgs, 2, None, ctypes.byref(ctx)) == _lib.AF_ERR_UNSUPPORTED
+    cfgs[1].flags = 0
+    cfgs[1].ny = 3
+    assert L.af_init_batch(cfgs, 2, None, ctypes.byref(ctx)) == _lib.AF_ERR_ARG
+    cfgs[1].ny, cfgs[1].bg[0] = 8, 0.0
+    assert L.af_init_batch(cfgs, 2, None, ctypes.byref(ctx)) == _lib.AF_ERR_ARG
+    assert L.af_step_batch(None, None, None, 1) == _lib.AF_ERR_ARG
+    assert L.af_batch_info(None, None, 0) == -1
