@@ -3,8 +3,11 @@
 // cot_n = (d step / d state_n)^T cot_np1 at fixed dt.  The forward intermediates
 // (recovered centres W^C and the node increments of both durations) are recomputed
 // from state_n by the multi-kernel path's k_centre/k_incr; the reverse sweep then
-// runs in the opposite order of the forward dataflow, one thread per cell, with
-// FP64 atomics accumulating the scattered contributions:
+// runs in the opposite order of the forward dataflow, one thread per cell.  The
+// reverse of a gather stencil is a scatter: every block accumulates its scattered
+// contributions in an LDS window over its cells plus the reach of the stencil
+// (LDS FP64 atomics), then adds the window to global memory once (one global
+// atomic per window entry instead of one per contribution):
 //   k_adj_points   average update and space-time Simpson fluxes (transposed), then
 //                  for every target and duration the transposed transported point
 //                  update: density closure, Q2 evaluation of W and of the increments
@@ -33,6 +36,11 @@ struct AdjNodes {
         j = (j < 0) ? j + ny : (j >= ny ? j - ny : j);
         return (size_t)j * nx + i;
     }
+    __device__ __forceinline__ double comp(int fam, int i, int j, int q) const {
+        const size_t k = idx(i, j);
+        if (fam == F_C) return C[(size_t)q * nx * ny + k];
+        return s[4 + 4 * fam + q][k];
+    }
     __device__ __forceinline__ Prim<double> node(int fam, int i, int j) const {
         const size_t k = idx(i, j);
         if (fam == F_C) {
@@ -54,39 +62,49 @@ struct AdjInc {
     }
 };
 
-// Scatter targets of the reverse sweep.
-struct AdjOut {
-    double* S[16];      // cot_n
-    double* lC;         // 4 planes: adjoint of the recovered centres
-    double* lD;         // 24 planes: adjoint of the increments [tau][fam][var]
-    int nx, ny;
-    __device__ __forceinline__ size_t idx(int i, int j) const {
-        i = (i < 0) ? i + nx : (i >= nx ? i - nx : i);
-        j = (j < 0) ? j + ny : (j >= ny ? j - ny : j);
-        return (size_t)j * nx + i;
+// Scatter target of the reverse sweep: an LDS window of NPL planes over node-cells
+// [ri0, ri0 + RX) x [rj0, rj0 + RY) (unwrapped indices; the flush wraps them).
+// Planes: 0..11 point values (family * 4 + (rho, u, v, p)), 12..15 recovered
+// centres, 16..39 increments (tau * 12 + family * 3 + (u, v, p)).
+template <int NPL, int RX, int RY>
+struct LdsWin {
+    double* a;
+    int ri0, rj0;
+    __device__ __forceinline__ void add(int pl, int i, int j, double v) const {
+        atomicAdd(a + (pl * RY + (j - rj0)) * RX + (i - ri0), v);
     }
     // add g = (d rho, d u, d v, d p) to node fam of cell (i, j)
     __device__ __forceinline__ void node(int fam, int i, int j, const double g[4]) const {
-        const size_t k = idx(i, j);
-        if (fam == F_C) {
-            const size_t N = (size_t)nx * ny;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (g[q] != 0.0) atomicAdd(lC + q * N + k, g[q]);
-            return;
-        }
-        const int b = 4 + 4 * fam;
+        const int b = fam == F_C ? 12 : 4 * fam;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            if (g[q] != 0.0) atomicAdd(S[b + q] + k, g[q]);
+            if (g[q] != 0.0) add(b + q, i, j, g[q]);
     }
     __device__ __forceinline__ void inc(int t, int fam, int i, int j, const double g[3]) const {
-        const size_t k = idx(i, j), N = (size_t)nx * ny;
 #pragma unroll
         for (int q = 0; q < 3; ++q)
-            if (g[q] != 0.0) atomicAdd(lD + (size_t)(t * 12 + fam * 3 + q) * N + k, g[q]);
+            if (g[q] != 0.0) add(16 + t * 12 + fam * 3 + q, i, j, g[q]);
+    }
+    __device__ __forceinline__ void zero() const {
+        for (int e = threadIdx.x; e < NPL * RX * RY; e += blockDim.x) a[e] = 0.0;
     }
 };
+
+struct PlaneList { double* p[40]; };
+
+// Add an LDS window to its global planes (periodic wrap), one atomic per nonzero entry.
+template <int NPL, int RX, int RY>
+__device__ __forceinline__ void flush_window(const LdsWin<NPL, RX, RY>& w, const PlaneList& G, int nx, int ny) {
+    for (int e = threadIdx.x; e < NPL * RX * RY; e += blockDim.x) {
+        const double v = w.a[e];
+        if (v == 0.0) continue;
+        const int pl = e / (RX * RY), r = e - pl * (RX * RY);
+        int i = w.ri0 + r % RX, j = w.rj0 + r / RX;
+        i = (i % nx + nx) % nx;
+        j = (j % ny + ny) % ny;
+        atomicAdd(G.p[pl] + (size_t)j * nx + i, v);
+    }
+}
 
 // Node (family, cell offset) of entry [a][b] of cell (ci, cj) (Sec. 2 layout).
 __device__ __forceinline__ void node_of(int a, int b, int ci, int cj, int& fam, int& i, int& j) {
@@ -126,9 +144,13 @@ __device__ __forceinline__ void flux_y_T(const Prim<double>& w, double gamma, co
 
 // Transposed transported point update (scheme 0) of target FAM at (i, j) for the
 // duration tau = lam h; lw = adjoint of the new point value.
-template <int FAM>
-__device__ void point_update_adj(const AdjNodes& A, const AdjInc& D, const AdjOut& O, int t, int i, int j,
-                                 double gamma, double lam, const double lw[4]) {
+// The forward value w is recomputed here and its cotangent formed from the flux
+// cotangents: lw = ws * (dF/dW)^T nuF + ws * (dG/dW)^T nuG (+ extra: the cotangent
+// of the new point value itself, for the full step).
+template <int FAM, class O_>
+__device__ void point_update_adj(const AdjNodes& A, const AdjInc& D, const O_& O, int t, int i, int j,
+                                 double gamma, double lam, const double nuF[4], const double nuG[4], double ws,
+                                 const double* extra) {
     const double ox = FamOffset<FAM>::ox, oy = FamOffset<FAM>::oy;
     const Prim<double> WP = A.node(FAM, i, j);
     unsigned st = 0;
@@ -186,6 +208,24 @@ __device__ void point_update_adj(const AdjNodes& A, const AdjInc& D, const AdjOu
     // ---- reverse ----
     // compose: rho = rho_f + dp rho_f / (gamma p_f), u = u_f + du, v = v_f + dv, p = p_f + dp
     const double qinv = 1.0 / (gamma * Wf[3]);
+    double lw[4] = {0.0, 0.0, 0.0, 0.0};
+    {
+        const Prim<double> w{Wf[0] + Df[2] * (Wf[0] * qinv), Wf[1] + Df[0], Wf[2] + Df[1], Wf[3] + Df[2]};
+        double nu[4];
+        if constexpr (FAM != F_EH) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) nu[k] = ws * nuF[k];
+            flux_x_T(w, gamma, nu, lw);
+        }
+        if constexpr (FAM != F_EV) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) nu[k] = ws * nuG[k];
+            flux_y_T(w, gamma, nu, lw);
+        }
+        if (extra)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) lw[k] += extra[k];
+    }
     double lWf[4], lDf[3];
     lWf[0] = lw[0] * (1.0 + Df[2] * qinv);
     lWf[1] = lw[1];
@@ -230,97 +270,91 @@ __device__ void point_update_adj(const AdjNodes& A, const AdjInc& D, const AdjOu
     O.node(FAM, i, j, gP);
 }
 
-struct PlaneList { double* p[40]; };
-
 __global__ void __launch_bounds__(256) k_adj_zero_list(PlaneList L, int nplanes, size_t N) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < N; k += stride)
         for (int p = 0; p < nplanes; ++p) L.p[p][k] = 0.0;
 }
 
-__global__ void __launch_bounds__(256) k_adj_points(StatePtrs<double> prim, const double* C, const double* Dfwd,
-                                                    StatePtrs<double> cot1, AdjOut O, double gamma, double lam0,
-                                                    double lam1) {
-    const int nx = O.nx, ny = O.ny;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= nx || j >= ny) return;
+// Reverse sweep of one target (family FAM of node-cell (i, j)): the adjoints of the
+// edge fluxes it feeds, from the averages' cotangents, then of its three time levels
+// (w^n directly, w^{n+1/2} and w^{n+1} through the transposed point update).
+template <int FAM, class O_>
+__device__ void point_adj_target(const StatePtrs<double>& prim, const double* C, const double* Dfwd,
+                                 const StatePtrs<double>& cot1, const O_& O, int nx, int ny, int i, int j,
+                                 double gamma, double lam0, double lam1) {
     AdjNodes A{{}, C, nx, ny};
 #pragma unroll
     for (int k = 0; k < 16; ++k) A.s[k] = prim.p[k];
     const size_t N = (size_t)nx * ny;
     AdjInc D0{Dfwd, nx, ny}, D1{Dfwd + 12 * N, nx, ny};
-    const PolAbs<double> pol{gamma, 1.0 / (gamma - 1.0)};
     auto lU = [&](int a, int b, int k) -> double { return cot1.p[k][A.idx(a, b)]; };
-    // adjoints of the time-integrated edge fluxes touching this cell's nodes
-    double nuFV[4], nuGV[4], nuFE[4], nuGE[4];
+    // cotangents of the time-integrated edge fluxes at this node: F at V and Ev, G at
+    // V and Eh; spatial Simpson weights 1/6 (V, two edges each) and 4/6 (edge midpoints)
+    double nuF[4] = {0, 0, 0, 0}, nuG[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const double muF_ij = lam1 * (lU(i, j, k) - lU(i - 1, j, k));
-        const double muF_ijm = lam1 * (lU(i, j - 1, k) - lU(i - 1, j - 1, k));
         const double muG_ij = lam1 * (lU(i, j, k) - lU(i, j - 1, k));
-        const double muG_imj = lam1 * (lU(i - 1, j, k) - lU(i - 1, j - 1, k));
-        nuFV[k] = (muF_ij + muF_ijm) * (1.0 / 6.0);
-        nuGV[k] = (muG_ij + muG_imj) * (1.0 / 6.0);
-        nuFE[k] = muF_ij * (4.0 / 6.0);
-        nuGE[k] = muG_ij * (4.0 / 6.0);
+        if constexpr (FAM == F_V) {
+            const double muF_ijm = lam1 * (lU(i, j - 1, k) - lU(i - 1, j - 1, k));
+            const double muG_imj = lam1 * (lU(i - 1, j, k) - lU(i - 1, j - 1, k));
+            nuF[k] = (muF_ij + muF_ijm) * (1.0 / 6.0);
+            nuG[k] = (muG_ij + muG_imj) * (1.0 / 6.0);
+        } else if constexpr (FAM == F_EV) {
+            nuF[k] = muF_ij * (4.0 / 6.0);
+        } else {
+            nuG[k] = muG_ij * (4.0 / 6.0);
+        }
     }
-    const double wsig[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+    // time level n (time-Simpson weight 1/6): the node itself
+    {
+        const Prim<double> w0 = A.node(FAM, i, j);
+        double g[4] = {0.0, 0.0, 0.0, 0.0}, nu[4];
+        if constexpr (FAM != F_EH) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) nu[k] = nuF[k] * (1.0 / 6.0);
+            flux_x_T(w0, gamma, nu, g);
+        }
+        if constexpr (FAM != F_EV) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) nu[k] = nuG[k] * (1.0 / 6.0);
+            flux_y_T(w0, gamma, nu, g);
+        }
+        O.node(FAM, i, j, g);
+    }
+    // n + 1/2 (weight 4/6) and n + 1 (weight 1/6; also an output of the step)
+    point_update_adj<FAM>(A, D0, O, 0, i, j, gamma, lam0, nuF, nuG, 4.0 / 6.0, nullptr);
     const size_t c = A.idx(i, j);
-    unsigned st = 0;
-#pragma unroll
-    for (int fam = 0; fam < 3; ++fam) {
-        Prim<double> w[3];
-        w[0] = A.node(fam, i, j);
-        if (fam == F_V) {
-            w[1] = point_update<F_V, 0>(A, D0, i, j, pol, lam0, st);
-            w[2] = point_update<F_V, 0>(A, D1, i, j, pol, lam1, st);
-        } else if (fam == F_EV) {
-            w[1] = point_update<F_EV, 0>(A, D0, i, j, pol, lam0, st);
-            w[2] = point_update<F_EV, 0>(A, D1, i, j, pol, lam1, st);
-        } else {
-            w[1] = point_update<F_EH, 0>(A, D0, i, j, pol, lam0, st);
-            w[2] = point_update<F_EH, 0>(A, D1, i, j, pol, lam1, st);
-        }
-        double lw[3][4];
-#pragma unroll
-        for (int sg = 0; sg < 3; ++sg) {
-            double nu[4];
-            double g[4] = {0.0, 0.0, 0.0, 0.0};
-            if (fam == F_V) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) nu[k] = wsig[sg] * nuFV[k];
-                flux_x_T(w[sg], gamma, nu, g);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) nu[k] = wsig[sg] * nuGV[k];
-                flux_y_T(w[sg], gamma, nu, g);
-            } else if (fam == F_EV) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) nu[k] = wsig[sg] * nuFE[k];
-                flux_x_T(w[sg], gamma, nu, g);
-            } else {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) nu[k] = wsig[sg] * nuGE[k];
-                flux_y_T(w[sg], gamma, nu, g);
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) lw[sg][k] = g[k];
-        }
-        // the new point value is also an output of the step
-#pragma unroll
-        for (int k = 0; k < 4; ++k) lw[2][k] += cot1.p[4 + 4 * fam + k][c];
-        O.node(fam, i, j, lw[0]);
-        if (fam == F_V) {
-            point_update_adj<F_V>(A, D0, O, 0, i, j, gamma, lam0, lw[1]);
-            point_update_adj<F_V>(A, D1, O, 1, i, j, gamma, lam1, lw[2]);
-        } else if (fam == F_EV) {
-            point_update_adj<F_EV>(A, D0, O, 0, i, j, gamma, lam0, lw[1]);
-            point_update_adj<F_EV>(A, D1, O, 1, i, j, gamma, lam1, lw[2]);
-        } else {
-            point_update_adj<F_EH>(A, D0, O, 0, i, j, gamma, lam0, lw[1]);
-            point_update_adj<F_EH>(A, D1, O, 1, i, j, gamma, lam1, lw[2]);
-        }
+    const double extra[4] = {cot1.p[4 + 4 * FAM][c], cot1.p[5 + 4 * FAM][c], cot1.p[6 + 4 * FAM][c],
+                             cot1.p[7 + 4 * FAM][c]};
+    point_update_adj<FAM>(A, D1, O, 1, i, j, gamma, lam1, nuF, nuG, 1.0 / 6.0, extra);
+}
+
+// Reverse of the point update, fluxes and average update for a BX x BY block of
+// cells, one thread per (cell, target family).  Feet stay within one cell (guarded),
+// so every contribution lands on node-cells [-1, B + 2) of the block: the LDS window.
+constexpr int kPBX = 16, kPBY = 8, kPNT = 3 * kPBX * kPBY;
+constexpr int kPRX = kPBX + 3, kPRY = kPBY + 3;
+using PointWin = LdsWin<40, kPRX, kPRY>;
+
+__global__ void __launch_bounds__(kPNT) k_adj_points(StatePtrs<double> prim, const double* C, const double* Dfwd,
+                                                     StatePtrs<double> cot1, PlaneList G, int nx, int ny,
+                                                     double gamma, double lam0, double lam1) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int i0 = blockIdx.x * kPBX, j0 = blockIdx.y * kPBY;
+    const PointWin O{reinterpret_cast<double*>(smem), i0 - 1, j0 - 1};
+    O.zero();
+    __syncthreads();
+    const int cell = (int)threadIdx.x % (kPBX * kPBY), fam = (int)threadIdx.x / (kPBX * kPBY);   // wave-uniform
+    const int i = i0 + cell % kPBX, j = j0 + cell / kPBX;
+    if (i < nx && j < ny) {
+        if (fam == F_V) point_adj_target<F_V>(prim, C, Dfwd, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
+        else if (fam == F_EV) point_adj_target<F_EV>(prim, C, Dfwd, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
+        else point_adj_target<F_EH>(prim, C, Dfwd, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
     }
+    __syncthreads();
+    flush_window(O, G, nx, ny);
 }
 
 // Transposed 1-D Lagrange-to-monomial transform (see mono1): (lc0, lc1, lc2) -> (lf0, lf1, lf2).
@@ -333,8 +367,8 @@ __device__ __forceinline__ void mono1_T(double c0, double c1, double c2, double&
 
 // Transposed wedge: adjoint of the accumulators -> adjoint of the cell's nodal (p, u, v),
 // scattered to the nodes of cell (ci, cj).
-template <int W, int XC, int YC>
-__device__ __forceinline__ void wedge_adj(const double la[6][4], const AdjOut& O, int ci, int cj) {
+template <int W, int XC, int YC, class O_>
+__device__ __forceinline__ void wedge_adj(const double la[6][4], const O_& O, int ci, int cj) {
     double lc[3][3][3];
 #pragma unroll
     for (int v = 0; v < 3; ++v)
@@ -383,16 +417,17 @@ __device__ __forceinline__ void wedge_adj(const double la[6][4], const AdjOut& O
         }
 }
 
-template <int FAM>
-__device__ void incr_adj(const AdjNodes& A, const AdjOut& O, int i, int j, double gamma, double lam0, double lam1) {
-    const size_t N = (size_t)O.nx * O.ny, k = A.idx(i, j);
+template <int FAM, class O_>
+__device__ void incr_adj(const AdjNodes& A, const O_& O, const double* lD, int i, int j, double gamma, double lam0,
+                         double lam1) {
+    const size_t N = (size_t)A.nx * A.ny, k = A.idx(i, j);
     double li[2][3];
     bool any = false;
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            li[t][q] = O.lD[(size_t)(t * 12 + FAM * 3 + q) * N + k];
+            li[t][q] = lD[(size_t)(t * 12 + FAM * 3 + q) * N + k];
             any = any || (li[t][q] != 0.0);
         }
     if (!any) return;
@@ -461,18 +496,33 @@ __device__ void incr_adj(const AdjNodes& A, const AdjOut& O, int i, int j, doubl
     }
 }
 
-__global__ void __launch_bounds__(256) k_adj_incr(StatePtrs<double> prim, const double* C, AdjOut O, double gamma,
-                                                  double lam0, double lam1) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= O.nx || j >= O.ny) return;
-    AdjNodes A{{}, C, O.nx, O.ny};
+// Transposed node increments for a BX x BY block of node-cells; every wedge's cell
+// lies in [-1, B] and its nodes in node-cells [-1, B + 1): the LDS window
+// (point-value and centre planes).
+constexpr int kIBX = 32, kIBY = 8;
+using IncrWin = LdsWin<16, kIBX + 2, kIBY + 2>;
+
+__global__ void __launch_bounds__(kIBX * kIBY) k_adj_incr(StatePtrs<double> prim, const double* C, const double* lD,
+                                                          PlaneList G, int nx, int ny, double gamma, double lam0,
+                                                          double lam1) {
+    __shared__ double win[16 * (kIBX + 2) * (kIBY + 2)];
+    const int i0 = blockIdx.x * kIBX, j0 = blockIdx.y * kIBY;
+    const IncrWin O{win, i0 - 1, j0 - 1};
+    O.zero();
+    __syncthreads();
+    const int i = i0 + (int)threadIdx.x % kIBX;
+    const int j = j0 + (int)threadIdx.x / kIBX;
+    if (i < nx && j < ny) {
+        AdjNodes A{{}, C, nx, ny};
 #pragma unroll
-    for (int k = 0; k < 16; ++k) A.s[k] = prim.p[k];
-    incr_adj<F_V>(A, O, i, j, gamma, lam0, lam1);
-    incr_adj<F_EV>(A, O, i, j, gamma, lam0, lam1);
-    incr_adj<F_EH>(A, O, i, j, gamma, lam0, lam1);
-    incr_adj<F_C>(A, O, i, j, gamma, lam0, lam1);
+        for (int k = 0; k < 16; ++k) A.s[k] = prim.p[k];
+        incr_adj<F_V>(A, O, lD, i, j, gamma, lam0, lam1);
+        incr_adj<F_EV>(A, O, lD, i, j, gamma, lam0, lam1);
+        incr_adj<F_EH>(A, O, lD, i, j, gamma, lam0, lam1);
+        incr_adj<F_C>(A, O, lD, i, j, gamma, lam0, lam1);
+    }
+    __syncthreads();
+    flush_window(O, G, nx, ny);
 }
 
 __device__ __forceinline__ void cons_T(const Prim<double>& w, double gamma, const double lU[4], double g[4]) {
@@ -484,42 +534,56 @@ __device__ __forceinline__ void cons_T(const Prim<double>& w, double gamma, cons
     g[3] = lU[3] / (gamma - 1.0);
 }
 
-__global__ void __launch_bounds__(256) k_adj_centre(StatePtrs<double> prim, const double* C, StatePtrs<double> cot1,
-                                                    AdjOut O, double gamma) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    if (i >= O.nx || j >= O.ny) return;
-    AdjNodes A{{}, C, O.nx, O.ny};
+// Transposed centre recovery for a BX x BY block of cells: writes the average planes
+// of cot_n and scatters into the point values of each cell's eight boundary nodes
+// (node-cells [0, B + 1): the LDS window).
+constexpr int kCBX = 32, kCBY = 8;
+using CentreWin = LdsWin<12, kCBX + 1, kCBY + 1>;
+
+__global__ void __launch_bounds__(kCBX * kCBY) k_adj_centre(StatePtrs<double> prim, const double* C, const double* lC,
+                                                            StatePtrs<double> cot1, StatePtrs<double> cot0,
+                                                            PlaneList G, int nx, int ny, double gamma) {
+    __shared__ double win[12 * (kCBX + 1) * (kCBY + 1)];
+    const int i0 = blockIdx.x * kCBX, j0 = blockIdx.y * kCBY;
+    const CentreWin O{win, i0, j0};
+    O.zero();
+    __syncthreads();
+    const int i = i0 + (int)threadIdx.x % kCBX;
+    const int j = j0 + (int)threadIdx.x / kCBX;
+    if (i < nx && j < ny) {
+        AdjNodes A{{}, C, nx, ny};
 #pragma unroll
-    for (int k = 0; k < 16; ++k) A.s[k] = prim.p[k];
-    const size_t N = (size_t)O.nx * O.ny, c = A.idx(i, j);
-    const double lW[4] = {O.lC[c], O.lC[N + c], O.lC[2 * N + c], O.lC[3 * N + c]};
-    const Prim<double> Wc = A.node(F_C, i, j);
-    // W = prim(U_c): rho = U0, u = U1/U0, v = U2/U0, p = (g-1)(U3 - (U1 u + U2 v)/2)
-    const double ir = 1.0 / Wc.r, gm1 = gamma - 1.0;
-    double lU[4];
-    lU[0] = lW[0] - lW[1] * Wc.u * ir - lW[2] * Wc.v * ir + lW[3] * gm1 * 0.5 * (Wc.u * Wc.u + Wc.v * Wc.v);
-    lU[1] = lW[1] * ir - lW[3] * gm1 * Wc.u;
-    lU[2] = lW[2] * ir - lW[3] * gm1 * Wc.v;
-    lU[3] = lW[3] * gm1;
-    // U_c = 9/4 [Ubar - sum_corners U / 36 - sum_edges U / 9]
+        for (int k = 0; k < 16; ++k) A.s[k] = prim.p[k];
+        const size_t N = (size_t)nx * ny, c = A.idx(i, j);
+        const double lW[4] = {lC[c], lC[N + c], lC[2 * N + c], lC[3 * N + c]};
+        const Prim<double> Wc = A.node(F_C, i, j);
+        // W = prim(U_c): rho = U0, u = U1/U0, v = U2/U0, p = (g-1)(U3 - (U1 u + U2 v)/2)
+        const double ir = 1.0 / Wc.r, gm1 = gamma - 1.0;
+        double lU[4];
+        lU[0] = lW[0] - lW[1] * Wc.u * ir - lW[2] * Wc.v * ir + lW[3] * gm1 * 0.5 * (Wc.u * Wc.u + Wc.v * Wc.v);
+        lU[1] = lW[1] * ir - lW[3] * gm1 * Wc.u;
+        lU[2] = lW[2] * ir - lW[3] * gm1 * Wc.v;
+        lU[3] = lW[3] * gm1;
+        // U_c = 9/4 [Ubar - sum_corners U / 36 - sum_edges U / 9]
 #pragma unroll
-    for (int k = 0; k < 4; ++k) O.S[k][c] = cot1.p[k][c] + 2.25 * lU[k];
-    double lc[4], le[4], g[4];
+        for (int k = 0; k < 4; ++k) cot0.p[k][c] = cot1.p[k][c] + 2.25 * lU[k];
+        double lc[4], le[4], g[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) { lc[k] = -lU[k] * (1.0 / 16.0); le[k] = -lU[k] * 0.25; }
-    cons_T(A.node(F_V, i, j), gamma, lc, g);          O.node(F_V, i, j, g);
-    cons_T(A.node(F_V, i + 1, j), gamma, lc, g);      O.node(F_V, i + 1, j, g);
-    cons_T(A.node(F_V, i, j + 1), gamma, lc, g);      O.node(F_V, i, j + 1, g);
-    cons_T(A.node(F_V, i + 1, j + 1), gamma, lc, g);  O.node(F_V, i + 1, j + 1, g);
-    cons_T(A.node(F_EH, i, j), gamma, le, g);         O.node(F_EH, i, j, g);
-    cons_T(A.node(F_EH, i, j + 1), gamma, le, g);     O.node(F_EH, i, j + 1, g);
-    cons_T(A.node(F_EV, i, j), gamma, le, g);         O.node(F_EV, i, j, g);
-    cons_T(A.node(F_EV, i + 1, j), gamma, le, g);     O.node(F_EV, i + 1, j, g);
+        for (int k = 0; k < 4; ++k) { lc[k] = -lU[k] * (1.0 / 16.0); le[k] = -lU[k] * 0.25; }
+        cons_T(A.node(F_V, i, j), gamma, lc, g);          O.node(F_V, i, j, g);
+        cons_T(A.node(F_V, i + 1, j), gamma, lc, g);      O.node(F_V, i + 1, j, g);
+        cons_T(A.node(F_V, i, j + 1), gamma, lc, g);      O.node(F_V, i, j + 1, g);
+        cons_T(A.node(F_V, i + 1, j + 1), gamma, lc, g);  O.node(F_V, i + 1, j + 1, g);
+        cons_T(A.node(F_EH, i, j), gamma, le, g);         O.node(F_EH, i, j, g);
+        cons_T(A.node(F_EH, i, j + 1), gamma, le, g);     O.node(F_EH, i, j + 1, g);
+        cons_T(A.node(F_EV, i, j), gamma, le, g);         O.node(F_EV, i, j, g);
+        cons_T(A.node(F_EV, i + 1, j), gamma, le, g);     O.node(F_EV, i + 1, j, g);
+    }
+    __syncthreads();
+    flush_window(O, G, nx, ny);
 }
 
 hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1_[16], void* const cot0_[16]) {
-    dim3 blk(64, 4), grd((a.nx + 63) / 64, (a.ny + 3) / 4);
     const size_t N = (size_t)a.nx * a.ny;
     double* C = (double*)a.scratch;
     double* Dfwd = C + 4 * N;
@@ -539,19 +603,32 @@ hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1_[16], vo
     for (int k = 0; k < 4; ++k) L.p[np++] = lC + k * N;
     for (int k = 0; k < 24; ++k) L.p[np++] = lD + k * N;
     hipLaunchKernelGGL(k_adj_zero_list, dim3(1024), dim3(256), 0, a.stream, L, np, N);
-    AdjOut O;
-    for (int k = 0; k < 16; ++k) O.S[k] = cot0.p[k];
-    O.lC = lC;
-    O.lD = lD;
-    O.nx = a.nx;
-    O.ny = a.ny;
+    // L now lists the window planes in LdsWin order: point values, centres, increments
     const double lam1 = a.dt / a.h, lam0 = 0.5 * lam1;
     if (a.ev_begin) (void)hipEventRecord(a.ev_begin, a.stream);
-    hipLaunchKernelGGL(k_adj_points, grd, blk, 0, a.stream, prim, C, Dfwd, cot1, O, a.gamma, lam0, lam1);
-    hipLaunchKernelGGL(k_adj_incr, grd, blk, 0, a.stream, prim, C, O, a.gamma, lam0, lam1);
-    hipLaunchKernelGGL(k_adj_centre, grd, blk, 0, a.stream, prim, C, cot1, O, a.gamma);
+    {
+        const size_t lds = sizeof(double) * 40 * kPRX * kPRY;   // allowed by prepare_adjoint_f64
+        dim3 grd((a.nx + kPBX - 1) / kPBX, (a.ny + kPBY - 1) / kPBY);
+        hipLaunchKernelGGL(k_adj_points, grd, dim3(kPNT), lds, a.stream, prim, C, Dfwd, cot1, L, a.nx, a.ny,
+                           a.gamma, lam0, lam1);
+    }
+    {
+        dim3 grd((a.nx + kIBX - 1) / kIBX, (a.ny + kIBY - 1) / kIBY);
+        hipLaunchKernelGGL(k_adj_incr, grd, dim3(kIBX * kIBY), 0, a.stream, prim, C, lD, L, a.nx, a.ny, a.gamma,
+                           lam0, lam1);
+    }
+    {
+        dim3 grd((a.nx + kCBX - 1) / kCBX, (a.ny + kCBY - 1) / kCBY);
+        hipLaunchKernelGGL(k_adj_centre, grd, dim3(kCBX * kCBY), 0, a.stream, prim, C, lC, cot1, cot0, L, a.nx,
+                           a.ny, a.gamma);
+    }
     if (a.ev_end) (void)hipEventRecord(a.ev_end, a.stream);
     return hipGetLastError();
+}
+
+hipError_t prepare_adjoint_f64() {
+    return hipFuncSetAttribute((const void*)k_adj_points, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(sizeof(double) * 40 * kPRX * kPRY));
 }
 
 size_t scratch_bytes_adjoint_f64(int nx, int ny) { return (size_t)nx * ny * (4 + 24 + 4 + 24) * sizeof(double); }

@@ -305,6 +305,7 @@ af_status af_init(const af_config* cfg, void* hip_stream, af_ctx** out) {
     if (e == hipSuccess && c->f32) e = hipMalloc(&c->comp, 4 * c->N * sizeof(float));
     if (e == hipSuccess && c->f32) e = hipMemsetAsync(c->comp, 0, 4 * c->N * sizeof(float), c->stream);
     if (e == hipSuccess && !c->f32 && c->variant == 0) e = af::prepare_fused_f64();
+    if (e == hipSuccess && !c->f32) e = af::prepare_adjoint_f64();
     if (e == hipSuccess && c->variant == 2) e = af::prepare_split_f64();
     if (e == hipSuccess) e = hipMalloc(&c->state2, 16 * c->N * c->elem);
     if (e == hipSuccess) e = hipMalloc(&c->scratch, sbytes);

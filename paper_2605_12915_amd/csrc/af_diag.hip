@@ -61,16 +61,21 @@ struct DiagAcc {
         j = j >= ny ? j - ny : j;
         return (size_t)j * nx + i;
     }
-    __device__ __forceinline__ Prim<double> node(int fam, int i, int j) const {
-        size_t k = idx(i, j);
-        if (fam == F_C) {
-            double Ub[4] = {val(0, k), val(1, k), val(2, k), val(3, k)};
-            return recover_centre(Ub, node(F_V, i, j), node(F_V, i + 1, j), node(F_V, i, j + 1),
-                                  node(F_V, i + 1, j + 1), node(F_EH, i, j), node(F_EH, i, j + 1),
-                                  node(F_EV, i, j), node(F_EV, i + 1, j), gamma);
-        }
+    __device__ __forceinline__ Prim<double> point(int fam, int i, int j) const {
+        const size_t k = idx(i, j);
         const int b = 4 + 4 * fam;
         return {val(b, k), val(b + 1, k), val(b + 2, k), val(b + 3, k)};
+    }
+    // (not recursive, so that it inlines: a call would spill the whole state)
+    __device__ __forceinline__ Prim<double> node(int fam, int i, int j) const {
+        if (fam == F_C) {
+            const size_t k = idx(i, j);
+            double Ub[4] = {val(0, k), val(1, k), val(2, k), val(3, k)};
+            return recover_centre(Ub, point(F_V, i, j), point(F_V, i + 1, j), point(F_V, i, j + 1),
+                                  point(F_V, i + 1, j + 1), point(F_EH, i, j), point(F_EH, i, j + 1),
+                                  point(F_EV, i, j), point(F_EV, i + 1, j), gamma);
+        }
+        return point(fam, i, j);
     }
 };
 
@@ -91,17 +96,22 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag(StatePtrs<const T> st, int 
     const double wq[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
     for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(c % nx), j = (int)(c / nx);
+#pragma unroll
         for (int k = 0; k < 4; ++k) v[k] += A.val(k, c);
         Prim<double> n[3][3];
         cell_nodes<double>(A, i, j, n);
         double e = 0.0;
+        // fully unrolled: a runtime index into n[][] would put it in private memory
+#pragma unroll
         for (int a = 0; a < 3; ++a)
+#pragma unroll
             for (int b = 0; b < 3; ++b) {
                 const Prim<double>& w = n[a][b];
                 e += wq[a] * wq[b] * w.r * (log(w.p) - gamma * log(w.r));
             }
         v[4] -= e;
         const Prim<double> own[4] = {n[0][0], n[0][1], n[1][0], n[1][1]};   // V, EV, EH, C of cell (i,j)
+#pragma unroll
         for (int f = 0; f < 4; ++f) {
             const Prim<double>& w = own[f];
             double cs = sqrt(gamma * w.p / w.r);

@@ -34,6 +34,7 @@ hipError_t launch_step_fused_f64(const StepArgs& a);
 hipError_t launch_step_fused_f32(const StepArgs& a);
 hipError_t prepare_fused_f32();
 hipError_t prepare_fused_f64();
+hipError_t prepare_adjoint_f64();
 size_t fused_lds_bytes();
 hipError_t launch_step_split_f64(const StepArgs& a);
 hipError_t prepare_split_f64();
