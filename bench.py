@@ -317,6 +317,10 @@ def main():
     tot_ms, ker_ms = st.time_steps(x, dt, 20)
     diag = st.diagnostics(x, dt)
     ok = bool(np.isfinite(diag["mass"]))
+    t0 = time.perf_counter()
+    for _ in range(10):
+        st.diagnostics(x, dt)                              # synchronous FP64 reductions
+    diag_ms = (time.perf_counter() - t0) * 1e3 / 10
     kname = st.dominant_kernel()
     flops = perf.ALGO_FLOPS_PER_CELL_F64 * ncell            # per launch of the step kernel
     achieved = flops / (ker_ms * 1e-3) / 1e12
@@ -340,6 +344,8 @@ def main():
                      "hbm_gbs_algorithmic": perf.ALGO_BYTES_PER_CELL_F64 * ncell / (ker_ms * 1e-3) / 1e9,
                      "t_alu_ms": t_alu * 1e3, "t_hbm_ms": t_hbm * 1e3},
         "finite": ok,
+        "diagnostics_ms": diag_ms,
+        "value_with_diagnostics_every_step": ncell * args.steps / (el + args.steps * diag_ms * 1e-3) / 1e6,
     }
     st.close()
     del x
