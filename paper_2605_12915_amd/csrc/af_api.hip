@@ -53,7 +53,7 @@ struct af_ctx {
     std::vector<const void*> btraj;          // per-instance state of the current trajectory
     int2* d_work = nullptr;
     int nwork = 0, tune_cfg = -1, grid = 0;
-    double tune_ms[af::kNumBatchCfgs] = {0, 0, 0, 0};
+    double tune_ms[af::kNumBatchCfgs] = {};
     hipStream_t cap = nullptr;               // internal stream for graph capture and replay
     hipEvent_t bev[2] = {nullptr, nullptr};
     std::map<int, hipGraphExec_t> graphs;    // nsteps -> instantiated graph
@@ -172,7 +172,7 @@ hipError_t batch_build_work(af_ctx* c, int cfg) {
     if (e == hipSuccess) e = af::batch_occupancy(cfg, &per_cu);
     hipDeviceProp_t prop;
     if (e == hipSuccess) e = hipGetDeviceProperties(&prop, c->device);
-    c->grid = (per_cu > 0 ? per_cu : 1) * prop.multiProcessorCount;
+    c->grid = t.direct ? c->nwork : (per_cu > 0 ? per_cu : 1) * prop.multiProcessorCount;
     return e;
 }
 
@@ -604,15 +604,16 @@ int32_t af_batch_info(af_ctx* c, char* buf, int32_t buflen) {
     if (c->tune_cfg >= 0) {
         const af::BatchTileCfg t = af::kBatchCfgs[c->tune_cfg];
         s += "[" + std::to_string(t.tx) + ", " + std::to_string(t.ty) + ", " + std::to_string(t.nt) + "]";
+        s += std::string(", \"mode\": \"") + (t.direct ? "direct" : "persistent") + "\"";
     } else {
         s += "null";
     }
     s += ", \"candidates\": [";
     for (int k = 0; k < af::kNumBatchCfgs; ++k) {
         const af::BatchTileCfg t = af::kBatchCfgs[k];
-        char tmp[160];
-        std::snprintf(tmp, sizeof(tmp), "%s{\"tile\": [%d, %d, %d], \"ms_per_step\": %.6f}", k ? ", " : "", t.tx, t.ty,
-                      t.nt, c->tune_ms[k]);
+        char tmp[200];
+        std::snprintf(tmp, sizeof(tmp), "%s{\"tile\": [%d, %d, %d], \"mode\": \"%s\", \"ms_per_step\": %.6f}",
+                      k ? ", " : "", t.tx, t.ty, t.nt, t.direct ? "direct" : "persistent", c->tune_ms[k]);
         s += tmp;
     }
     s += "]}";
@@ -626,8 +627,8 @@ const char* af_dominant_kernel(af_ctx* c) {
     if (c && c->nbatch) {
         if (c->tune_cfg < 0) return "af::k_fused_batch (tile not chosen yet)";
         const af::BatchTileCfg t = af::kBatchCfgs[c->tune_cfg];
-        c->kname = "af::k_fused_batch<" + std::to_string(t.tx) + ", " + std::to_string(t.ty) + ", " +
-                   std::to_string(t.nt) + ">";
+        c->kname = std::string(t.direct ? "af::k_fused_batch_direct<" : "af::k_fused_batch<") + std::to_string(t.tx) +
+                   ", " + std::to_string(t.ty) + ", " + std::to_string(t.nt) + ">";
         return c->kname.c_str();
     }
     const bool rb = c && (c->cfg.flags & AF_SCHEME_RB);

@@ -1,12 +1,12 @@
-// Batching form: many FP32 grids of uneven sizes stepped by ONE persistent launch per
-// step.  The work list holds every (instance, tile) pair of the batch; a grid of
+// Batching form: many FP32 grids of uneven sizes stepped by ONE launch per step.  The work list holds every (instance, tile) pair of the batch; a grid of
 // (CUs x resident workgroups) persistent workgroups walks contiguous chunks of it
 // (chunks numbered XCD-aware, so a workgroup's neighbours in the list run on the
 // same XCD), calling the same fused tile computation as the single-grid kernel,
 // with each instance's own size, background, dt and buffers read from a device
 // descriptor array.  af_step_batch captures nsteps launches (alternating the ping-
 // pong direction) in a hipGraph and replays it.  The tile shape comes from the
-// autotuner (af_api.hip), which times every instantiation below on the batch.
+// autotuner (af_api.hip), which times every instantiation below on the batch, in
+// both grid modes: persistent (the loop above) and direct (one workgroup per item).
 #include <hip/hip_runtime.h>
 
 #include "af_batch.h"
@@ -54,6 +54,31 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     if (st) atomicOr(status, st);
 }
 
+// Direct grid mode: one workgroup per work item (the hardware dispatcher balances the
+// load), tile body inlined exactly as in the single-grid kernel.  Work items are
+// numbered XCD-aware: each XCD gets a contiguous run of the list.
+template <int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) k_fused_batch_direct(const BatchInst* __restrict__ inst,
+                                                           const int2* __restrict__ work, int nwork, int parity,
+                                                           unsigned* status) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    auto& L = *reinterpret_cast<FusedTile<float, TX, TY>*>(smem);
+    int w;
+    {
+        const int b = blockIdx.x, xcd = b & 7;
+        int base = 0;
+        for (int x = 0; x < xcd; ++x) base += (nwork - x + 7) >> 3;
+        w = base + (b >> 3);
+    }
+    const int2 it = work[w];
+    const BatchInst& d = inst[it.x];
+    const PlaneView in{{d.S[parity]}}, out{{d.S[parity ^ 1]}};
+    unsigned st = 0;
+    fused_tile<float, PolPert<float>, TX, TY, NT, 0, true>(L, in, out, d.comp, d.nx, d.ny, (it.y % d.tiles_x) * TX,
+                                                           (it.y / d.tiles_x) * TY, d.pol, d.lam0, d.lam1, st);
+    if (st) atomicOr(status, st);
+}
+
 // partner -> caller's buffer for every instance (the odd-step tail of a captured sequence).
 __global__ void __launch_bounds__(256) k_batch_copy(const BatchInst* inst, int n) {
     for (int q = 0; q < n; ++q) {
@@ -65,48 +90,60 @@ __global__ void __launch_bounds__(256) k_batch_copy(const BatchInst* inst, int n
 }
 
 template <int TX, int TY, int NT>
-static hipError_t launch_cfg(const BatchInst* inst, const int2* work, int nwork, int parity, unsigned* status,
-                             int grid, hipStream_t s) {
+static hipError_t launch_cfg(bool direct, const BatchInst* inst, const int2* work, int nwork, int parity,
+                             unsigned* status, int grid, hipStream_t s) {
     const size_t lds = sizeof(FusedTile<float, TX, TY>);
-    hipLaunchKernelGGL((k_fused_batch<TX, TY, NT>), dim3(grid), dim3(NT), lds, s, inst, work, nwork, parity, status);
+    if (direct)
+        hipLaunchKernelGGL((k_fused_batch_direct<TX, TY, NT>), dim3(nwork), dim3(NT), lds, s, inst, work, nwork, parity,
+                           status);
+    else
+        hipLaunchKernelGGL((k_fused_batch<TX, TY, NT>), dim3(grid), dim3(NT), lds, s, inst, work, nwork, parity, status);
     return hipGetLastError();
 }
 
 template <int TX, int TY, int NT>
-static hipError_t occupancy_cfg(int* blocks_per_cu) {
+static hipError_t occupancy_cfg(bool direct, int* blocks_per_cu) {
     const size_t lds = sizeof(FusedTile<float, TX, TY>);
+    if (direct)
+        return hipFuncSetAttribute((const void*)k_fused_batch_direct<TX, TY, NT>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipError_t e = hipFuncSetAttribute((const void*)k_fused_batch<TX, TY, NT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused_batch<TX, TY, NT>, NT, lds);
 }
 
+// Candidates: six tile shapes in the persistent mode, then the same six direct.
 const BatchTileCfg kBatchCfgs[kNumBatchCfgs] = {
-    {32, 8, 512}, {32, 8, 256}, {32, 16, 512}, {32, 16, 256}, {64, 8, 512}, {16, 16, 256},
+    {32, 8, 512, false}, {32, 8, 256, false}, {32, 16, 512, false}, {32, 16, 256, false}, {64, 8, 512, false},
+    {16, 16, 256, false}, {32, 8, 512, true},  {32, 8, 256, true},  {32, 16, 512, true},  {32, 16, 256, true},
+    {64, 8, 512, true},   {16, 16, 256, true},
 };
 
-hipError_t batch_occupancy(int cfg, int* blocks_per_cu) {
-    switch (cfg) {
-        case 0: return occupancy_cfg<32, 8, 512>(blocks_per_cu);
-        case 1: return occupancy_cfg<32, 8, 256>(blocks_per_cu);
-        case 2: return occupancy_cfg<32, 16, 512>(blocks_per_cu);
-        case 3: return occupancy_cfg<32, 16, 256>(blocks_per_cu);
-        case 4: return occupancy_cfg<64, 8, 512>(blocks_per_cu);
-        default: return occupancy_cfg<16, 16, 256>(blocks_per_cu);
+#define AF_BATCH_SWITCH(F, ...)                                   \
+    {                                                             \
+        const bool direct = cfg >= 6;                             \
+        switch (cfg % 6) {                                        \
+            case 0: return F<32, 8, 512>(direct, __VA_ARGS__);    \
+            case 1: return F<32, 8, 256>(direct, __VA_ARGS__);    \
+            case 2: return F<32, 16, 512>(direct, __VA_ARGS__);   \
+            case 3: return F<32, 16, 256>(direct, __VA_ARGS__);   \
+            case 4: return F<64, 8, 512>(direct, __VA_ARGS__);    \
+            default: return F<16, 16, 256>(direct, __VA_ARGS__); \
+        }                                                         \
     }
+
+hipError_t batch_occupancy(int cfg, int* blocks_per_cu) {
+    *blocks_per_cu = 1;
+    AF_BATCH_SWITCH(occupancy_cfg, blocks_per_cu)
 }
 
 hipError_t launch_batch(int cfg, const BatchInst* inst, const int2* work, int nwork, int parity, unsigned* status,
                         int grid, hipStream_t s) {
-    switch (cfg) {
-        case 0: return launch_cfg<32, 8, 512>(inst, work, nwork, parity, status, grid, s);
-        case 1: return launch_cfg<32, 8, 256>(inst, work, nwork, parity, status, grid, s);
-        case 2: return launch_cfg<32, 16, 512>(inst, work, nwork, parity, status, grid, s);
-        case 3: return launch_cfg<32, 16, 256>(inst, work, nwork, parity, status, grid, s);
-        case 4: return launch_cfg<64, 8, 512>(inst, work, nwork, parity, status, grid, s);
-        default: return launch_cfg<16, 16, 256>(inst, work, nwork, parity, status, grid, s);
-    }
+    AF_BATCH_SWITCH(launch_cfg, inst, work, nwork, parity, status, grid, s)
 }
+
+#undef AF_BATCH_SWITCH
 
 hipError_t launch_batch_copy(const BatchInst* inst, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_copy, dim3(1024), dim3(256), 0, s, inst, n);

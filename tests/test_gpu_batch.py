@@ -55,7 +55,7 @@ def single(torch_dev, P, x, dt, n):
     return y
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("cfg", list(range(12)))
 def test_batch_tile_cfg_matches_single_grid(torch_dev, cfg, monkeypatch):
     torch, dev = torch_dev
     from paper_2605_12915_amd.stepper import Batch
@@ -152,9 +152,10 @@ def test_batch_autotuner_report(torch_dev):
     assert all(t > 0 for t in times)
     best = min(range(len(times)), key=lambda k: times[k])
     assert info["chosen"] == info["candidates"][best]["tile"]
+    assert info["mode"] == info["candidates"][best]["mode"]
     tx, ty = info["chosen"][0], info["chosen"][1]
     assert info["work_items"] == sum(-(-P.nx // tx) * -(-P.ny // ty) for P in Ps)
-    assert info["grid"] >= 256
+    assert info["grid"] >= (info["work_items"] if info["mode"] == "direct" else 256)
     # tuning ran on copies: the step result equals stepping from the original states
     want = [single(torch_dev, P, x, P.dt_for_cfl(0.4), 2) for P, x in zip(Ps, before)]
     for g, w in zip(xs, want):
