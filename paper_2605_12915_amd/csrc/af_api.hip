@@ -633,8 +633,8 @@ const char* af_dominant_kernel(af_ctx* c) {
     }
     const bool rb = c && (c->cfg.flags & AF_SCHEME_RB);
     if (c && c->f32)
-        return rb ? "af::k_fused<float, af::PolPert<float>, 32, 8, 512, 1, true>"
-                  : "af::k_fused<float, af::PolPert<float>, 32, 8, 512, 0, true>";
+        return rb ? "af::k_fused<float, af::PolPert<float>, 32, 16, 512, 1, true>"
+                  : "af::k_fused<float, af::PolPert<float>, 32, 16, 512, 0, true>";
     if (c && c->variant == 1) return "af_step multi-kernel sequence";
     if (c && c->variant == 2) return rb ? "af::k_points_update<32, 8, 512, 1>" : "af::k_points_update<32, 8, 512, 0>";
     return rb ? "af::k_fused<double, af::PolAbs<double>, 32, 8, 512, 1, false>"

@@ -11,7 +11,7 @@
 
 namespace af {
 
-constexpr int kFTX = 32, kFTY = 8, kFNT = 512;
+constexpr int kFTX = 32, kFTY = 16, kFNT = 512;
 
 PolPert<float> pert_pol_f32(const double bg[4], double g) {
     const double r0 = bg[0], u0 = bg[1], v0 = bg[2], p0 = bg[3];
