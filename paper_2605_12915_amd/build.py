@@ -28,13 +28,24 @@ FLAGS = [
 CONTRACT_ON = {"af_fused_f32.hip", "af_batch.hip"}
 
 
+# Backend options for the device code only (a plain -mllvm would also reach the host
+# compile, whose target does not know them): the GCN max-ILP machine scheduler, 1.5-3%
+# faster on the step, FP32 and adjoint kernels than the default.  The device pass writes
+# the offload bundle that the host pass embeds.
+DEVICE_ONLY = ["-mllvm", "-misched=gcn-max-ilp"]
+
+
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    dev = os.path.join(OBJ, os.path.basename(src) + ".hipfb")
     contract = "-ffp-contract=on" if os.path.basename(src) in CONTRACT_ON else "-ffp-contract=fast"
-    cmd = [HIPCC, *FLAGS, contract, "-c", src, "-o", obj]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    cmds = [[HIPCC, *FLAGS, contract, "--cuda-device-only", *DEVICE_ONLY, "-c", src, "-o", dev],
+            [HIPCC, *FLAGS, contract, "--cuda-host-only", "-Xclang", "-fcuda-include-gpubinary", "-Xclang", dev,
+             "-c", src, "-o", obj]]
+    for cmd in cmds:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
     return obj
 
 

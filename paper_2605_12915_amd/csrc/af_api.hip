@@ -19,7 +19,7 @@ namespace {
 
 thread_local int g_last_hip = 0;
 
-constexpr int kDiagPartials = 1024;
+constexpr int kDiagPartials = 4096;   // blocks of the first reduction pass
 
 }  // namespace
 

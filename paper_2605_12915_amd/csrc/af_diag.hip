@@ -3,44 +3,27 @@
 // Two passes: a grid-stride block reduction into per-block partials (wavefront
 // shuffles, then LDS across the block's wavefronts), then one block over the
 // partials.  Entropy uses the tensor Simpson rule over the nine Q2 nodes of a cell
-// (the recovered centre included).
+// (the recovered centre included), regrouped per node.
 #include <hip/hip_runtime.h>
 
 #include "af_internal.h"
 #include "af_kernels.h"
+#include "af_reduce.h"
 
 namespace af {
 
-constexpr int kDiagVals = 9;   // 5 sums, min rho, min p, max(|u|+c), max c
 constexpr int kDiagBlock = 256;
 
-struct DiagBg { double bg[4], Ubg[4]; };
-
-__device__ __forceinline__ void combine(double* a, const double* b) {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) a[k] += b[k];
-    a[5] = fmin(a[5], b[5]);
-    a[6] = fmin(a[6], b[6]);
-    a[7] = fmax(a[7], b[7]);
-    a[8] = fmax(a[8], b[8]);
-}
 
 __device__ __forceinline__ void block_reduce(double v[kDiagVals], double* sh) {
-    // within the wavefront
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        double o[kDiagVals];
-#pragma unroll
-        for (int k = 0; k < kDiagVals; ++k) o[k] = __shfl_down(v[k], off, 64);
-        combine(v, o);
-    }
+    diag_wave_reduce(v);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0)
 #pragma unroll
         for (int k = 0; k < kDiagVals; ++k) sh[wid * kDiagVals + k] = v[k];
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) combine(v, sh + w * kDiagVals);
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) diag_combine(v, sh + w * kDiagVals);
     }
 }
 
@@ -93,33 +76,28 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag(StatePtrs<const T> st, int 
     for (int k = 0; k < 16; ++k) A.s[k] = st.p[k];
     double v[kDiagVals] = {0, 0, 0, 0, 0, 1e300, 1e300, 0, 0};
     const size_t N = (size_t)nx * ny;
-    const double wq[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
-    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(c % nx), j = (int)(c / nx);
+    // Entropy: the tensor Simpson rule over the nine Q2 nodes of every cell, summed
+    // over cells, gives each node the sum of its weights in the cells that share it:
+    // vertex 4 x 1/36 = 1/9, edge midpoints 2 x 4/36 = 2/9, centre 16/36 = 4/9.  So
+    // each cell evaluates its own four nodes (V, Ev, Eh, C) once.
+    const double wnode[4] = {kWNodeV, kWNodeE, kWNodeE, kWNodeC};
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += stride) {
+        // 32-bit division when the grid allows (64-bit division costs ~10x more)
+        int i, j;
+        if (N <= 0xffffffffull) {
+            const unsigned cu = (unsigned)c, nxu = (unsigned)nx;
+            j = (int)(cu / nxu);
+            i = (int)(cu - (unsigned)j * nxu);
+        } else {
+            i = (int)(c % nx);
+            j = (int)(c / nx);
+        }
 #pragma unroll
         for (int k = 0; k < 4; ++k) v[k] += A.val(k, c);
-        Prim<double> n[3][3];
-        cell_nodes<double>(A, i, j, n);
-        double e = 0.0;
-        // fully unrolled: a runtime index into n[][] would put it in private memory
+        const Prim<double> own[4] = {A.point(F_V, i, j), A.point(F_EV, i, j), A.point(F_EH, i, j), A.node(F_C, i, j)};
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const Prim<double>& w = n[a][b];
-                e += wq[a] * wq[b] * w.r * (log(w.p) - gamma * log(w.r));
-            }
-        v[4] -= e;
-        const Prim<double> own[4] = {n[0][0], n[0][1], n[1][0], n[1][1]};   // V, EV, EH, C of cell (i,j)
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            const Prim<double>& w = own[f];
-            double cs = sqrt(gamma * w.p / w.r);
-            v[5] = fmin(v[5], w.r);
-            v[6] = fmin(v[6], w.p);
-            v[7] = fmax(v[7], sqrt(w.u * w.u + w.v * w.v) + cs);
-            v[8] = fmax(v[8], cs);
-        }
+        for (int f = 0; f < 4; ++f) diag_node(v, wnode[f], own[f].r, own[f].u, own[f].v, own[f].p, gamma);
     }
     block_reduce(v, sh);
     if (threadIdx.x == 0)
@@ -129,15 +107,15 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag(StatePtrs<const T> st, int 
 __global__ void __launch_bounds__(kDiagBlock) k_diag_final(const double* partials, int n, double* out) {
     __shared__ double sh[(kDiagBlock / 64) * kDiagVals];
     double v[kDiagVals] = {0, 0, 0, 0, 0, 1e300, 1e300, 0, 0};
-    for (int b = threadIdx.x; b < n; b += blockDim.x) combine(v, partials + (size_t)b * kDiagVals);
+    for (int b = threadIdx.x; b < n; b += blockDim.x) diag_combine(v, partials + (size_t)b * kDiagVals);
     block_reduce(v, sh);
     if (threadIdx.x == 0)
         for (int k = 0; k < kDiagVals; ++k) out[k] = v[k];
 }
 
-hipError_t launch_diag(const void* const s[16], bool f32, const double bg[4], int nx, int ny, double h,
-                       double gamma, double* partials, int npartials, double* out9, hipStream_t stream) {
+DiagBg diag_bg(bool f32, const double bg[4], double gamma) {
     DiagBg b;
+    b.gamma = gamma;
     for (int k = 0; k < 4; ++k) { b.bg[k] = f32 ? bg[k] : 0.0; b.Ubg[k] = 0.0; }
     if (f32) {
         b.Ubg[0] = bg[0];
@@ -145,6 +123,17 @@ hipError_t launch_diag(const void* const s[16], bool f32, const double bg[4], in
         b.Ubg[2] = bg[0] * bg[2];
         b.Ubg[3] = bg[3] / (gamma - 1.0) + 0.5 * bg[0] * (bg[1] * bg[1] + bg[2] * bg[2]);
     }
+    return b;
+}
+
+hipError_t launch_diag_final(const double* partials, int n, double* out9, hipStream_t stream) {
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagBlock), 0, stream, partials, n, out9);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(const void* const s[16], bool f32, const double bg[4], int nx, int ny, double h,
+                       double gamma, double* partials, int npartials, double* out9, hipStream_t stream) {
+    const DiagBg b = diag_bg(f32, bg, gamma);
     if (f32) {
         StatePtrs<const float> st;
         for (int k = 0; k < 16; ++k) st.p[k] = (const float*)s[k];

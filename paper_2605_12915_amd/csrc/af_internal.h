@@ -26,6 +26,15 @@ struct StepArgs {
     void* comp;                 // FP32 path: 4 compensation planes of the average update
 };
 
+// Diagnostics partials: 9 values per block (5 sums, min rho, min p, max(|u|+c),
+// max c), reduced by launch_diag_final.
+constexpr int kDiagVals = 9;
+// Background of an FP32 state (zeros for FP64): absolute = stored + bg (points),
+// stored + Ubg (averages).
+struct DiagBg { double bg[4], Ubg[4], gamma; };
+DiagBg diag_bg(bool f32, const double bg[4], double gamma);
+hipError_t launch_diag_final(const double* partials, int n, double* out9, hipStream_t stream);
+
 hipError_t launch_step_multi_f64(const StepArgs& a);
 hipError_t launch_intermediates_f64(const StepArgs& a, double* C, double* D);
 hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1[16], void* const cot0[16]);

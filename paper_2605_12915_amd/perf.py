@@ -29,10 +29,12 @@ FP32_PEAK_TFLOPS = 157.3
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 
-# Sources whose change invalidates a stored counter measurement of a kernel.
+# Files whose change invalidates a stored counter measurement of a kernel (its
+# sources, and the build script that holds the compiler flags), relative to the package.
 KERNEL_SOURCES = {
-    "af::k_fused<double, af::PolAbs<double>, 32, 8, 512, 0, false>":
-        ["af_fused.hip", "af_fused.h", "af_kernels.h", "af_device.h", "af_blocks.h", "af_internal.h"],
+    "af::k_fused<double, af::PolAbs<double>, 32, 8, 512, 0, false, false>":
+        ["csrc/af_fused.hip", "csrc/af_fused.h", "csrc/af_kernels.h", "csrc/af_device.h", "csrc/af_blocks.h",
+         "csrc/af_internal.h", "build.py"],
 }
 
 
@@ -42,7 +44,7 @@ def source_sha(kernel: str) -> str | None:
         return None
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+        with open(os.path.join(HERE, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
