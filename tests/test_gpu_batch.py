@@ -15,6 +15,8 @@ import pytest
 
 from paper_2605_12915_amd import inputs as I
 
+from tests.f32bound import f32_tolerance
+
 pytestmark = pytest.mark.gpu
 
 
@@ -84,17 +86,12 @@ def test_batch_vs_oracle(torch_dev, orc):
     b = Batch(grids_of(Ps), check_errors=True, device=dev)
     b.step(xs, dts, 12)
     torch.cuda.synchronize()
-    eps32 = float(np.finfo(np.float32).eps)
     for P, x, dt in zip(Ps, xs, dts):
-        want = orc.run(P.state(), P.h, P.gamma, dt, 12)
+        s0 = P.state()
+        want = orc.run(s0, P.h, P.gamma, dt, 12)
         got = from_perturbation(x.cpu().numpy(), P.bg, P.gamma)
-        # FP32 form's stated accuracy, per plane: within 2e-5 of the perturbation's
-        # range, or within 2 ulps of the absolute field (what storing the absolute
-        # state in FP32 would give) where that is larger -- the low-Mach shear layer's
-        # density and pressure perturbations are O(M^2) of their background.
         err = np.abs(got - want).max(axis=(1, 2))
-        rng = want.max(axis=(1, 2)) - want.min(axis=(1, 2))
-        tol = 2e-5 * rng + 2 * eps32 * np.abs(want).max(axis=(1, 2))
+        tol = f32_tolerance(want, s0, P.bg, P.gamma, 12)
         print(P.name, P.nx, P.ny, "batch vs oracle: max err/tol", (err / tol).max())
         assert np.all(err <= tol), np.array2string(err / tol, precision=2)
 
@@ -180,3 +177,29 @@ def test_batch_errors(torch_dev):
     assert e.value.code == AF_ERR_ACOUSTIC_CFL
     with pytest.raises(ValueError):
         b.step(xs[:2], dts[:2], 1)
+
+
+def test_batch_config5_full_size_one_step(torch_dev, orc):
+    """The benchmark's batch (64 double shear layers, sizes N in [32, 1024]) in the
+    tuned launch configuration, one step, every grid against the oracle."""
+    torch, dev = torch_dev
+    from paper_2605_12915_amd.stepper import Batch, from_perturbation
+    sizes = I.batch_sizes(64)
+    Ps = [I.double_shear_layer(N) for N in sizes]
+    dts = [P.dt_for_cfl(0.4) for P in Ps]
+    s0 = [P.state() for P in Ps]
+    from paper_2605_12915_amd.stepper import to_perturbation
+    xs = [torch.from_numpy(to_perturbation(s, P.bg, P.gamma)).to(dev) for s, P in zip(s0, Ps)]
+    b = Batch(grids_of(Ps), check_errors=True, device=dev)
+    b.step(xs, dts, 1)
+    torch.cuda.synchronize()
+    print("config 5 tuned tile", b.info()["chosen"], b.info()["mode"], flush=True)
+    worst = 0.0
+    for P, s, x, dt in zip(Ps, s0, xs, dts):
+        want = orc.step(s, P.h, P.gamma, dt)
+        got = from_perturbation(x.cpu().numpy(), P.bg, P.gamma)
+        err = np.abs(got - want).max(axis=(1, 2))
+        tol = f32_tolerance(want, s, P.bg, P.gamma, 1)
+        worst = max(worst, float((err / tol).max()))
+        assert np.all(err <= tol), (P.nx, np.array2string(err / tol, precision=2))
+    print("config 5 worst err/tol", worst)

@@ -7,6 +7,8 @@ import pytest
 
 from paper_2605_12915_amd import inputs as I
 
+from tests.f32bound import f32_tolerance
+
 pytestmark = pytest.mark.gpu
 
 
@@ -101,3 +103,19 @@ def test_f32_diagnostics(torch_dev, orc):
     want = orc.diagnostics(s0, P.h, P.gamma, dt)
     for k, v in want.items():
         assert abs(got[k] - v) <= 1e-6 * max(1.0, abs(v)), (k, got[k], v)
+
+
+def test_f32_config3_full_size_one_step(torch_dev, orc):
+    """4096^2 (both sub-cases of the FP32 benchmark), one step from the same state:
+    every output against the oracle at the FP32 form's bound (the oracle runs the full
+    grid on the host cores)."""
+    for P in (I.isentropic_vortex(4096, uinf=(1.0, 1.0)), I.gaussian_pulse(4096, amp=0.1, width=0.05)):
+        s0 = P.state()
+        dt = P.dt_for_cfl(0.4)
+        print(P.name, "4096^2: oracle step ...", flush=True)
+        want = orc.step(s0, P.h, P.gamma, dt)
+        got, _, _ = run_f32(torch_dev, P, s0, dt, 1, bg=P.bg)
+        err = np.abs(got - want).max(axis=(1, 2))
+        tol = f32_tolerance(want, s0, P.bg, P.gamma, 1)
+        print(P.name, "max err/tol", (err / tol).max(), flush=True)
+        assert np.all(err <= tol), np.array2string(err / tol, precision=2)
