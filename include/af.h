@@ -127,19 +127,20 @@ af_status af_time_steps(af_ctx* ctx, const af_state* s, double dt, int32_t nstep
 
 /* Batching form.  n grids (each described by its own af_config; all AF_F32, TAI
  * scheme) stepped together: every step is ONE kernel launch over the list of
- * (grid, tile) work items of the whole batch, and af_step_batch replays
- * nsteps such launches captured in a hipGraph (built on first use for each nsteps
- * and kept).  The tile shape is chosen by an autotuner on the first af_step_batch
- * call: every compiled tile configuration is timed on a copy of the batch's states
- * and the fastest is kept (af_batch_info reports the timings); the environment
- * variable AF_BATCH_TILE=k (0 <= k < 12), read by af_init_batch, fixes candidate k
- * instead.  Candidates (cells x cells / threads per workgroup): 32x8/512, 32x8/256,
- * 32x16/512, 32x16/256, 64x8/512, 16x16/256, first in the persistent grid mode (k < 6:
- * CUs x resident workgroups looping over the work list), then in the direct mode
- * (k >= 6: one workgroup per work item).  Each grid keeps its
- * own Kahan compensation planes, tied to the trajectory as for AF_F32 contexts.
- * The library allocates one partner state and four compensation planes per grid.
- * hip_stream is borrowed; replays run on an internal stream ordered after it. */
+ * (grid, tile) work items of the whole batch, and af_step_batch replays nsteps such
+ * launches captured in a hipGraph (built on first use for each nsteps and kept; at
+ * most 16 distinct nsteps are kept at a time).  The tile shape is chosen by an
+ * autotuner on the first af_step_batch call: every compiled candidate is timed on a
+ * copy of the batch's states and the fastest is kept (af_batch_info reports the
+ * timings); the environment variable AF_BATCH_TILE=k (0 <= k < 12), read by
+ * af_init_batch, fixes candidate k instead.  Candidates (cells x cells / threads per
+ * workgroup): 32x8/512, 32x8/256, 32x16/512, 32x16/256, 64x8/512, 16x16/256, first
+ * in the persistent grid mode (k < 6: CUs x resident workgroups looping over the
+ * work list), then in the direct mode (k >= 6: one workgroup per work item).  Each
+ * grid keeps its own Kahan compensation planes, tied to the trajectory as for AF_F32
+ * contexts.  The library allocates one partner state and four compensation planes
+ * per grid.  hip_stream is borrowed; replays run on an internal stream ordered after
+ * it. */
 af_status af_init_batch(const af_config* cfgs, int32_t n, void* hip_stream, af_ctx** out);
 /* (af_init_batch errors: AF_ERR_ARG for n outside 1..4096 or a config af_init would
  * reject; AF_ERR_UNSUPPORTED for a config that is not AF_F32 or asks for

@@ -3,7 +3,8 @@
 // cot_n = (d step / d state_n)^T cot_np1 at fixed dt.  The forward intermediates
 // (recovered centres W^C and the node increments of both durations) are recomputed
 // from state_n by the multi-kernel path's k_centre/k_incr; the reverse sweep then
-// runs in the opposite order of the forward dataflow, one thread per cell.  The
+// runs in the opposite order of the forward dataflow, one thread per cell (per cell
+// and target family in k_adj_points).  The
 // reverse of a gather stencil is a scatter: every block accumulates its scattered
 // contributions in an LDS window over its cells plus the reach of the stencil
 // (LDS FP64 atomics), then adds the window to global memory once (one global

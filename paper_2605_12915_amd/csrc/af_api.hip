@@ -46,8 +46,8 @@ struct af_ctx {
     std::vector<af_config> bcfg;
     std::vector<af::BatchInst> binst;        // host copy of the descriptors
     std::vector<af::BatchInst> bup;          // descriptors as last uploaded
-    int force_cfg = -1;
-    std::string kname;                       // af_dominant_kernel's text for batch contexts                      // AF_BATCH_TILE: fixed tile configuration, no tuning
+    int force_cfg = -1;                      // AF_BATCH_TILE: fixed tile configuration, no tuning
+    std::string kname;                       // af_dominant_kernel's text for batch contexts
     af::BatchInst* d_binst = nullptr;
     std::vector<void*> bbufs;                // per-instance partner states and compensation planes
     std::vector<const void*> btraj;          // per-instance state of the current trajectory
@@ -241,9 +241,19 @@ hipError_t batch_tune(af_ctx* c) {
     return e;
 }
 
+// Instantiated graphs are kept per nsteps; past kMaxGraphs distinct values the cache
+// is emptied (a caller cycling through many step counts should not grow it forever).
+constexpr size_t kMaxGraphs = 16;
+
 hipError_t batch_graph(af_ctx* c, int nsteps, hipGraphExec_t* out) {
     auto it = c->graphs.find(nsteps);
     if (it != c->graphs.end()) { *out = it->second; return hipSuccess; }
+    if (c->graphs.size() >= kMaxGraphs) {
+        hipError_t e = hipStreamSynchronize(c->cap);   // no replay may still be running
+        if (e != hipSuccess) return e;
+        for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+        c->graphs.clear();
+    }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
     for (int k = 0; k < nsteps && e == hipSuccess; ++k)
@@ -297,10 +307,10 @@ af_status af_init(const af_config* cfg, void* hip_stream, af_ctx** out) {
     c->variant = 0;
     if (v && std::strcmp(v, "multi") == 0) c->variant = 1;
     if (v && std::strcmp(v, "split") == 0) c->variant = 2;
+    if (c->f32) c->variant = 0;   // the FP32 form has the fused kernel only
     size_t sbytes = 16;
     if (c->variant == 1) sbytes = af::scratch_bytes_multi_f64(cfg->nx, cfg->ny);
     if (c->variant == 2) sbytes = af::scratch_bytes_split_f64(cfg->nx, cfg->ny);
-    if (c->f32) c->variant = 0;
     if (e == hipSuccess && c->f32) e = af::prepare_fused_f32();
     if (e == hipSuccess && c->f32) e = hipMalloc(&c->comp, 4 * c->N * sizeof(float));
     if (e == hipSuccess && c->f32) e = hipMemsetAsync(c->comp, 0, 4 * c->N * sizeof(float), c->stream);
