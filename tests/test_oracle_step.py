@@ -241,3 +241,28 @@ def test_vortex_third_order(orc):
         errs.append(math.sqrt(np.mean((out[0] - s[0]) ** 2)))
     orders = [math.log2(errs[k] / errs[k + 1]) for k in range(len(ns) - 1)]
     assert min(orders) > 2.6, (errs, orders)
+
+
+# ---------------------------------------------------------------------------
+# Convergence in the linear regime (Sec. 4.2): mixed entropy/shear/acoustic packet
+# ---------------------------------------------------------------------------
+
+def test_mixed_packet_third_order_points(orc):
+    """The linearised mixed packet (amplitudes 1e-6 about rho0 = p0 = 1, M = 0.2 at
+    25 degrees) has an exact solution: each wave travels at its own speed.  The point
+    values after T = 0.2 must converge to it at third order."""
+    T = 0.2
+    errs = []
+    ns = (16, 32, 64)
+    for n in ns:
+        P, at = I.mixed_packet(n)
+        s = P.state()
+        dt0 = P.dt_for_cfl(0.4)
+        nsteps = int(math.ceil(T / dt0))
+        out = orc.run(s, P.h, P.gamma, T / nsteps, nsteps)
+        exact = I.make_state(at(T), n, n, 0.0, 0.0, P.h, P.gamma)
+        errs.append(float(np.abs(out[4:] - exact[4:]).max()) / 1e-6)
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(len(ns) - 1)]
+    print("mixed packet point errors / eps", errs, "orders", orders)
+    assert errs[-1] < 0.05
+    assert min(orders) > 2.6, (errs, orders)
