@@ -59,6 +59,13 @@ __device__ __forceinline__ int wrap_any(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
+// Periodic index of the tile window: one conditional shift when the grid is at least
+// as large as the window (the usual case, decided per launch), else a modulo.
+__device__ __forceinline__ int wrap_win(int v, int n, bool one) {
+    if (one) return v < 0 ? v + n : (v >= n ? v - n : v);
+    return wrap_any(v, n);
+}
+
 // One tile: cells [i0, i0+TX) x [j0, j0+TY) of one grid.  Called by the single-grid
 // kernel (one tile per workgroup) and by the batched persistent kernel (a list of
 // tiles of many grids per workgroup).  The arithmetic of every node does not depend
@@ -78,10 +85,14 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
     using Tile = FusedTile<T, TX, TY>;
     const int tid = threadIdx.x;
 
+    // windows reach 2 cells below and 3 above the tile: one wrap suffices when the
+    // grid spans the window
+    const bool onex = nx >= Tile::PX, oney = ny >= Tile::PY;
+
     // ---- phase 0: primitive node values of cells [-2, T+3)^2 ------------------------
     for (int e = tid; e < Tile::PX * Tile::PY; e += NT) {
         const int x = e % Tile::PX, y = e / Tile::PX;
-        const size_t g = (size_t)wrap_any(j0 + y - 2, ny) * nx + wrap_any(i0 + x - 2, nx);
+        const size_t g = (size_t)wrap_win(j0 + y - 2, ny, oney) * nx + wrap_win(i0 + x - 2, nx, onex);
 #pragma unroll
         for (int k = 0; k < 12; ++k) L.P[k][y][x] = in.p[4 + k][g];
     }
@@ -92,7 +103,7 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
         LdsAcc<T, TX, TY> A{&L};
         for (int e = tid; e < Tile::CX * Tile::CY; e += NT) {
             const int x = e % Tile::CX - 2, y = e / Tile::CX - 2;
-            const size_t g = (size_t)wrap_any(j0 + y, ny) * nx + wrap_any(i0 + x, nx);
+            const size_t g = (size_t)wrap_win(j0 + y, ny, oney) * nx + wrap_win(i0 + x, nx, onex);
             const T Ub[4] = {in.p[0][g], in.p[1][g], in.p[2][g], in.p[3][g]};
             Prim<T> w = pol.centre(Ub, A.node(F_V, x, y), A.node(F_V, x + 1, y), A.node(F_V, x, y + 1),
                                    A.node(F_V, x + 1, y + 1), A.node(F_EH, x, y), A.node(F_EH, x, y + 1),
