@@ -614,7 +614,8 @@ int32_t af_batch_info(af_ctx* c, char* buf, int32_t buflen) {
     if (c->tune_cfg >= 0) {
         const af::BatchTileCfg t = af::kBatchCfgs[c->tune_cfg];
         s += "[" + std::to_string(t.tx) + ", " + std::to_string(t.ty) + ", " + std::to_string(t.nt) + "]";
-        s += std::string(", \"mode\": \"") + (t.direct ? "direct" : "persistent") + "\"";
+        s += std::string(", \"mode\": \"") + (t.direct ? "direct" : "persistent") + "\", \"min_waves\": " +
+             std::to_string(t.minw);
     } else {
         s += "null";
     }
@@ -622,8 +623,9 @@ int32_t af_batch_info(af_ctx* c, char* buf, int32_t buflen) {
     for (int k = 0; k < af::kNumBatchCfgs; ++k) {
         const af::BatchTileCfg t = af::kBatchCfgs[k];
         char tmp[200];
-        std::snprintf(tmp, sizeof(tmp), "%s{\"tile\": [%d, %d, %d], \"mode\": \"%s\", \"ms_per_step\": %.6f}",
-                      k ? ", " : "", t.tx, t.ty, t.nt, t.direct ? "direct" : "persistent", c->tune_ms[k]);
+        std::snprintf(tmp, sizeof(tmp),
+                      "%s{\"tile\": [%d, %d, %d], \"mode\": \"%s\", \"min_waves\": %d, \"ms_per_step\": %.6f}",
+                      k ? ", " : "", t.tx, t.ty, t.nt, t.direct ? "direct" : "persistent", t.minw, c->tune_ms[k]);
         s += tmp;
     }
     s += "]}";
@@ -638,17 +640,18 @@ const char* af_dominant_kernel(af_ctx* c) {
         if (c->tune_cfg < 0) return "af::k_fused_batch (tile not chosen yet)";
         const af::BatchTileCfg t = af::kBatchCfgs[c->tune_cfg];
         c->kname = std::string(t.direct ? "af::k_fused_batch_direct<" : "af::k_fused_batch<") + std::to_string(t.tx) +
-                   ", " + std::to_string(t.ty) + ", " + std::to_string(t.nt) + ">";
+                   ", " + std::to_string(t.ty) + ", " + std::to_string(t.nt) +
+                   (t.direct ? ", " + std::to_string(t.minw) : std::string()) + ">";
         return c->kname.c_str();
     }
     const bool rb = c && (c->cfg.flags & AF_SCHEME_RB);
     if (c && c->f32)
-        return rb ? "af::k_fused<float, af::PolPert<float>, 32, 16, 512, 1, true>"
-                  : "af::k_fused<float, af::PolPert<float>, 32, 16, 512, 0, true>";
+        return rb ? "af::k_fused<float, af::PolPert<float>, 32, 8, 512, 1, true, 4>"
+                  : "af::k_fused<float, af::PolPert<float>, 32, 8, 512, 0, true, 4>";
     if (c && c->variant == 1) return "af_step multi-kernel sequence";
     if (c && c->variant == 2) return rb ? "af::k_points_update<32, 8, 512, 1>" : "af::k_points_update<32, 8, 512, 0>";
-    return rb ? "af::k_fused<double, af::PolAbs<double>, 32, 8, 512, 1, false>"
-              : "af::k_fused<double, af::PolAbs<double>, 32, 8, 512, 0, false>";
+    return rb ? "af::k_fused<double, af::PolAbs<double>, 32, 8, 512, 1, false, 1>"
+              : "af::k_fused<double, af::PolAbs<double>, 32, 8, 512, 0, false, 1>";
 }
 
 }  // extern "C"

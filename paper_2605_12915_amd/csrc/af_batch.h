@@ -32,8 +32,8 @@ struct PlaneView {
     } p;
 };
 
-struct BatchTileCfg { int tx, ty, nt; bool direct; };
-constexpr int kNumBatchCfgs = 12;
+struct BatchTileCfg { int tx, ty, nt; bool direct; int minw; };
+constexpr int kNumBatchCfgs = 13;
 extern const BatchTileCfg kBatchCfgs[kNumBatchCfgs];
 
 hipError_t batch_occupancy(int cfg, int* blocks_per_cu);

@@ -57,8 +57,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
 // Direct grid mode: one workgroup per work item (the hardware dispatcher balances the
 // load), tile body inlined exactly as in the single-grid kernel.  Work items are
 // numbered XCD-aware: each XCD gets a contiguous run of the list.
-template <int TX, int TY, int NT>
-__global__ void __launch_bounds__(NT) k_fused_batch_direct(const BatchInst* __restrict__ inst,
+template <int TX, int TY, int NT, int MINW>
+__global__ void __launch_bounds__(NT, MINW) k_fused_batch_direct(const BatchInst* __restrict__ inst,
                                                            const int2* __restrict__ work, int nwork, int parity,
                                                            unsigned* status) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -89,23 +89,23 @@ __global__ void __launch_bounds__(256) k_batch_copy(const BatchInst* inst, int n
     }
 }
 
-template <int TX, int TY, int NT>
+template <int TX, int TY, int NT, int MINW = 1>
 static hipError_t launch_cfg(bool direct, const BatchInst* inst, const int2* work, int nwork, int parity,
                              unsigned* status, int grid, hipStream_t s) {
     const size_t lds = sizeof(FusedTile<float, TX, TY>);
     if (direct)
-        hipLaunchKernelGGL((k_fused_batch_direct<TX, TY, NT>), dim3(nwork), dim3(NT), lds, s, inst, work, nwork, parity,
-                           status);
+        hipLaunchKernelGGL((k_fused_batch_direct<TX, TY, NT, MINW>), dim3(nwork), dim3(NT), lds, s, inst, work, nwork,
+                           parity, status);
     else
         hipLaunchKernelGGL((k_fused_batch<TX, TY, NT>), dim3(grid), dim3(NT), lds, s, inst, work, nwork, parity, status);
     return hipGetLastError();
 }
 
-template <int TX, int TY, int NT>
+template <int TX, int TY, int NT, int MINW = 1>
 static hipError_t occupancy_cfg(bool direct, int* blocks_per_cu) {
     const size_t lds = sizeof(FusedTile<float, TX, TY>);
     if (direct)
-        return hipFuncSetAttribute((const void*)k_fused_batch_direct<TX, TY, NT>,
+        return hipFuncSetAttribute((const void*)k_fused_batch_direct<TX, TY, NT, MINW>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipError_t e = hipFuncSetAttribute((const void*)k_fused_batch<TX, TY, NT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -113,15 +113,18 @@ static hipError_t occupancy_cfg(bool direct, int* blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused_batch<TX, TY, NT>, NT, lds);
 }
 
-// Candidates: six tile shapes in the persistent mode, then the same six direct.
+// Candidates: six tile shapes in the persistent mode, the same six direct, and 32x8
+// direct with registers capped for 4 waves per SIMD (two workgroups per CU).
 const BatchTileCfg kBatchCfgs[kNumBatchCfgs] = {
-    {32, 8, 512, false}, {32, 8, 256, false}, {32, 16, 512, false}, {32, 16, 256, false}, {64, 8, 512, false},
-    {16, 16, 256, false}, {32, 8, 512, true},  {32, 8, 256, true},  {32, 16, 512, true},  {32, 16, 256, true},
-    {64, 8, 512, true},   {16, 16, 256, true},
+    {32, 8, 512, false, 1}, {32, 8, 256, false, 1}, {32, 16, 512, false, 1}, {32, 16, 256, false, 1},
+    {64, 8, 512, false, 1}, {16, 16, 256, false, 1}, {32, 8, 512, true, 1},   {32, 8, 256, true, 1},
+    {32, 16, 512, true, 1}, {32, 16, 256, true, 1},  {64, 8, 512, true, 1},   {16, 16, 256, true, 1},
+    {32, 8, 512, true, 4},
 };
 
 #define AF_BATCH_SWITCH(F, ...)                                   \
     {                                                             \
+        if (cfg == 12) return F<32, 8, 512, 4>(true, __VA_ARGS__); \
         const bool direct = cfg >= 6;                             \
         switch (cfg % 6) {                                        \
             case 0: return F<32, 8, 512>(direct, __VA_ARGS__);    \
@@ -129,7 +132,7 @@ const BatchTileCfg kBatchCfgs[kNumBatchCfgs] = {
             case 2: return F<32, 16, 512>(direct, __VA_ARGS__);   \
             case 3: return F<32, 16, 256>(direct, __VA_ARGS__);   \
             case 4: return F<64, 8, 512>(direct, __VA_ARGS__);    \
-            default: return F<16, 16, 256>(direct, __VA_ARGS__); \
+            default: return F<16, 16, 256>(direct, __VA_ARGS__);  \
         }                                                         \
     }
 

@@ -249,8 +249,10 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
 }
 
 // ---- single-grid kernel: one tile per workgroup --------------------------------------
-template <class T, class Pol, int TX, int TY, int NT, int SCHEME, bool KAHAN>
-__global__ void __launch_bounds__(NT) k_fused(StatePtrs<T> in, StatePtrs<T> out, T* comp, int nx, int ny,
+// MINW: minimum wavefronts per SIMD the register allocation must allow (1: no
+// constraint beyond the workgroup size; 4 at 512 threads: two workgroups per CU).
+template <class T, class Pol, int TX, int TY, int NT, int SCHEME, bool KAHAN, int MINW = 1>
+__global__ void __launch_bounds__(NT, MINW) k_fused(StatePtrs<T> in, StatePtrs<T> out, T* comp, int nx, int ny,
                                               int tiles_x, int ntiles, Pol pol, T lam0, T lam1, unsigned* status) {
     extern __shared__ __align__(16) unsigned char smem[];
     auto& L = *reinterpret_cast<FusedTile<T, TX, TY>*>(smem);
@@ -270,7 +272,7 @@ __global__ void __launch_bounds__(NT) k_fused(StatePtrs<T> in, StatePtrs<T> out,
 }
 
 
-template <class T, class Pol, int TX, int TY, int NT, bool KAHAN>
+template <class T, class Pol, int TX, int TY, int NT, bool KAHAN, int MINW = 1>
 hipError_t launch_fused(const StepArgs& a, const Pol& pol) {
     StatePtrs<T> in, out;
     for (int k = 0; k < 16; ++k) { in.p[k] = (T*)a.in[k]; out.p[k] = (T*)a.out[k]; }
@@ -281,22 +283,22 @@ hipError_t launch_fused(const StepArgs& a, const Pol& pol) {
     T* comp = (T*)a.comp;
     if (a.ev_begin) (void)hipEventRecord(a.ev_begin, a.stream);
     if (a.scheme == 0)
-        hipLaunchKernelGGL((k_fused<T, Pol, TX, TY, NT, 0, KAHAN>), dim3(ntiles), dim3(NT), lds, a.stream, in, out, comp,
+        hipLaunchKernelGGL((k_fused<T, Pol, TX, TY, NT, 0, KAHAN, MINW>), dim3(ntiles), dim3(NT), lds, a.stream, in, out, comp,
                            a.nx, a.ny, tiles_x, ntiles, pol, lam0, lam1, a.status);
     else
-        hipLaunchKernelGGL((k_fused<T, Pol, TX, TY, NT, 1, KAHAN>), dim3(ntiles), dim3(NT), lds, a.stream, in, out, comp,
+        hipLaunchKernelGGL((k_fused<T, Pol, TX, TY, NT, 1, KAHAN, MINW>), dim3(ntiles), dim3(NT), lds, a.stream, in, out, comp,
                            a.nx, a.ny, tiles_x, ntiles, pol, lam0, lam1, a.status);
     if (a.ev_end) (void)hipEventRecord(a.ev_end, a.stream);
     return hipGetLastError();
 }
 
-template <class T, class Pol, int TX, int TY, int NT, bool KAHAN>
+template <class T, class Pol, int TX, int TY, int NT, bool KAHAN, int MINW = 1>
 hipError_t prepare_fused() {
     const size_t lds = sizeof(FusedTile<T, TX, TY>);
-    hipError_t e = hipFuncSetAttribute((const void*)k_fused<T, Pol, TX, TY, NT, 0, KAHAN>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_fused<T, Pol, TX, TY, NT, 0, KAHAN, MINW>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_fused<T, Pol, TX, TY, NT, 1, KAHAN>,
+    return hipFuncSetAttribute((const void*)k_fused<T, Pol, TX, TY, NT, 1, KAHAN, MINW>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 

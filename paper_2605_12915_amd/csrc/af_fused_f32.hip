@@ -11,7 +11,9 @@
 
 namespace af {
 
-constexpr int kFTX = 32, kFTY = 16, kFNT = 512;
+// 32x8 cells, 512 threads, registers capped for 4 waves per SIMD: two 67 KB workgroups
+// share a CU (12% faster than one 32x16 workgroup with free register allocation).
+constexpr int kFTX = 32, kFTY = 8, kFNT = 512, kFMinW = 4;
 
 PolPert<float> pert_pol_f32(const double bg[4], double g) {
     const double r0 = bg[0], u0 = bg[1], v0 = bg[2], p0 = bg[3];
@@ -25,9 +27,9 @@ PolPert<float> pert_pol_f32(const double bg[4], double g) {
 }
 
 hipError_t launch_step_fused_f32(const StepArgs& a) {
-    return launch_fused<float, PolPert<float>, kFTX, kFTY, kFNT, true>(a, pert_pol_f32(a.bg, a.gamma));
+    return launch_fused<float, PolPert<float>, kFTX, kFTY, kFNT, true, kFMinW>(a, pert_pol_f32(a.bg, a.gamma));
 }
 
-hipError_t prepare_fused_f32() { return prepare_fused<float, PolPert<float>, kFTX, kFTY, kFNT, true>(); }
+hipError_t prepare_fused_f32() { return prepare_fused<float, PolPert<float>, kFTX, kFTY, kFNT, true, kFMinW>(); }
 
 }  // namespace af

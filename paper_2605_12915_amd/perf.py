@@ -32,7 +32,7 @@ ROOT = os.path.dirname(HERE)
 # Files whose change invalidates a stored counter measurement of a kernel (its
 # sources, and the build script that holds the compiler flags), relative to the package.
 KERNEL_SOURCES = {
-    "af::k_fused<double, af::PolAbs<double>, 32, 8, 512, 0, false, false>":
+    "af::k_fused<double, af::PolAbs<double>, 32, 8, 512, 0, false, 1>":
         ["csrc/af_fused.hip", "csrc/af_fused.h", "csrc/af_kernels.h", "csrc/af_device.h", "csrc/af_blocks.h",
          "csrc/af_internal.h", "build.py"],
 }
@@ -58,6 +58,7 @@ def stored_traffic(kernel: str):
     with open(path) as fh:
         data = json.load(fh)
     rec = data.get(kernel)
-    if not rec or rec.get("source_sha") != source_sha(kernel):
+    sha = source_sha(kernel)
+    if not rec or sha is None or rec.get("source_sha") != sha:
         return None
     return rec

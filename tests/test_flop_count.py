@@ -20,3 +20,15 @@ def test_flop_count_current(tmp_path):
     out = json.loads(subprocess.run([exe], check=True, capture_output=True, text=True).stdout)
     assert out["flops_per_cell_update"] == perf.ALGO_FLOPS_PER_CELL_F64
     assert out["sqrts"] == 4 and out["divs"] > 0
+
+
+def test_dominant_kernel_has_tracked_sources():
+    """The kernel the benchmark reports has a source list, so stored counters are
+    invalidated when its code changes (perf.stored_traffic)."""
+    import re
+    from paper_2605_12915_amd import perf
+    src = open(os.path.join(ROOT, "paper_2605_12915_amd", "csrc", "af_api.hip")).read()
+    names = re.findall(r'"(af::k_fused<double, af::PolAbs<double>, [^"]*, 0, [^"]*)"', src)
+    assert names, "dominant FP64 kernel name not found"
+    for n in names:
+        assert perf.source_sha(n) is not None, n
