@@ -1,0 +1,107 @@
+"""Pins of the oracle's diagnostics against closed forms (no GPU).
+
+* conservative totals are h^2 times the sums of the averages, which for data given by
+  cell averages of a periodic field equal its exact integrals;
+* the entropy functional -int rho log(p / rho^gamma) dA, discretised by the tensor
+  Simpson rule over the nine Q2 nodes of every cell (the recovered centre included),
+  converges at fourth order to the exact integral of a smooth non-isentropic field;
+* minima, maxima and the acoustic CFL number over the nodes are the extremes of the
+  sampled values.
+"""
+import math
+
+import numpy as np
+
+from paper_2605_12915_amd import inputs as I
+
+G = 1.4
+
+
+def field(xv, yv):
+    X, Y = np.meshgrid(xv, yv)
+    rho = 1.0 + 0.3 * np.sin(2 * math.pi * X) * np.sin(2 * math.pi * Y)
+    u = 0.2 * np.cos(2 * math.pi * Y)
+    v = -0.1 * np.sin(2 * math.pi * X)
+    p = 1.0 + 0.2 * np.cos(2 * math.pi * (X + Y))
+    return rho, u, v, p
+
+
+def exact_integrals():
+    """Gauss-Legendre tensor quadrature, 64 x 64 panels of 12 x 12 points: exact to
+    round-off for these trigonometric integrands."""
+    g, w = np.polynomial.legendre.leggauss(12)
+    panels = 64
+    x = ((np.arange(panels)[:, None] + 0.5 * (g[None, :] + 1.0)) / panels).reshape(-1)
+    wx = np.tile(0.5 * w / panels, panels)
+    rho, u, v, p = field(x, x)
+    W = np.outer(wx, wx)
+    E = p / (G - 1.0) + 0.5 * rho * (u * u + v * v)
+    return {"mass": float(np.sum(W * rho)), "momx": float(np.sum(W * rho * u)),
+            "momy": float(np.sum(W * rho * v)), "energy": float(np.sum(W * E)),
+            "entropy": float(-np.sum(W * rho * (np.log(p) - G * np.log(rho))))}
+
+
+def problem(n):
+    return I.Problem("diag_field", n, n, 0.0, 0.0, 1.0 / n, G, field)
+
+
+def test_totals_are_exact_integrals(orc):
+    ex = exact_integrals()
+    P = problem(24)
+    d = orc.diagnostics(P.state(), P.h, G, 1e-3)
+    for k in ("mass", "momx", "momy", "energy"):
+        # the 5x5 Gauss-Legendre cell averages integrate these smooth fields to ~1e-12
+        assert abs(d[k] - ex[k]) <= 1e-10 * max(1.0, abs(ex[k])), (k, d[k], ex[k])
+
+
+def test_entropy_fourth_order(orc):
+    ex = exact_integrals()["entropy"]
+    errs = []
+    for n in (8, 16, 32, 64):
+        P = problem(n)
+        errs.append(abs(orc.diagnostics(P.state(), P.h, G, 1e-3)["entropy"] - ex))
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
+    print("entropy errors", errs, "orders", orders)
+    # Simpson error ~ h^4 f^(4) / 180: 6e-9 at n = 64 for this field (|ex| = 0.041)
+    assert errs[-1] < 1e-8
+    assert min(orders[1:]) > 3.5, orders
+
+
+def _cons(w):
+    r, u, v, p = w
+    return np.stack([r, r * u, r * v, p / (G - 1.0) + 0.5 * r * (u * u + v * v)])
+
+
+def _prim(U):
+    r = U[0]
+    u, v = U[1] / r, U[2] / r
+    return np.stack([r, u, v, (G - 1.0) * (U[3] - 0.5 * r * (u * u + v * v))])
+
+
+def test_extremes_over_nodes(orc):
+    """Minima and maxima over the four node families, with the centre obtained here
+    from its defining condition: the 3x3 Simpson average of the Q2 interpolant of the
+    conserved variables equals the cell average (corner weight 1/36, edge 4/36,
+    centre 16/36)."""
+    n = 20
+    P = I.Problem("diag_field", n, n, 0.0127, 0.0311, 1.0 / n, G, field)
+    s = P.state()
+    dt = 2e-3
+    d = orc.diagnostics(s, P.h, G, dt)
+    UV, UEv, UEh = _cons(s[4:8]), _cons(s[8:12]), _cons(s[12:16])
+    sh = lambda a, dx, dy: np.roll(np.roll(a, -dy, axis=1), -dx, axis=2)
+    corners = UV + sh(UV, 1, 0) + sh(UV, 0, 1) + sh(UV, 1, 1)
+    edges = UEv + sh(UEv, 1, 0) + UEh + sh(UEh, 0, 1)
+    C = _prim((36.0 * s[0:4] - corners - 4.0 * edges) / 16.0)
+    fams = [s[4:8], s[8:12], s[12:16], C]
+    rho = np.concatenate([q[0].ravel() for q in fams])
+    p = np.concatenate([q[3].ravel() for q in fams])
+    cs = np.sqrt(G * p / rho)
+    spd = np.concatenate([np.hypot(q[1], q[2]).ravel() for q in fams]) + cs
+    assert np.isclose(d["min_rho"], rho.min(), rtol=1e-13, atol=0)
+    assert np.isclose(d["min_p"], p.min(), rtol=1e-13, atol=0)
+    assert np.isclose(d["max_speed"], spd.max(), rtol=1e-13, atol=0)
+    assert np.isclose(d["max_acoustic_r"], cs.max() * dt / P.h, rtol=1e-13, atol=0)
+    # the centres matter: without them the extremes differ for this field
+    nn = 3 * n * n
+    assert rho[nn:].min() < rho[:nn].min() or spd[nn:].max() > spd[:nn].max()
