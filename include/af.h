@@ -132,12 +132,13 @@ af_status af_time_steps(af_ctx* ctx, const af_state* s, double dt, int32_t nstep
  * most 16 distinct nsteps are kept at a time).  The tile shape is chosen by an
  * autotuner on the first af_step_batch call: every compiled candidate is timed on a
  * copy of the batch's states and the fastest is kept (af_batch_info reports the
- * timings); the environment variable AF_BATCH_TILE=k (0 <= k < 13), read by
+ * timings); the environment variable AF_BATCH_TILE=k (0 <= k < 14), read by
  * af_init_batch, fixes candidate k instead.  Candidates (cells x cells / threads per
  * workgroup): 32x8/512, 32x8/256, 32x16/512, 32x16/256, 64x8/512, 16x16/256, first
  * in the persistent grid mode (k < 6: CUs x resident workgroups looping over the
  * work list), then in the direct mode (6 <= k < 12: one workgroup per work item),
- * and k = 12: 32x8/512 direct with registers capped for two workgroups per CU.  Each
+ * and k = 12, 13: 32x8/512 and 24x13/512 direct with registers capped for two
+ * workgroups per CU.  Each
  * grid keeps its own Kahan compensation planes, tied to the trajectory as for AF_F32
  * contexts.  The library allocates one partner state and four compensation planes
  * per grid.  hip_stream is borrowed; replays run on an internal stream ordered after

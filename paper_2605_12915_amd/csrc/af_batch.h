@@ -33,7 +33,7 @@ struct PlaneView {
 };
 
 struct BatchTileCfg { int tx, ty, nt; bool direct; int minw; };
-constexpr int kNumBatchCfgs = 13;
+constexpr int kNumBatchCfgs = 14;
 extern const BatchTileCfg kBatchCfgs[kNumBatchCfgs];
 
 hipError_t batch_occupancy(int cfg, int* blocks_per_cu);

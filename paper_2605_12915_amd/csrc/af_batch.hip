@@ -113,18 +113,20 @@ static hipError_t occupancy_cfg(bool direct, int* blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused_batch<TX, TY, NT>, NT, lds);
 }
 
-// Candidates: six tile shapes in the persistent mode, the same six direct, and 32x8
-// direct with registers capped for 4 waves per SIMD (two workgroups per CU).
+// Candidates: six tile shapes in the persistent mode, the same six direct, and 32x8 and
+// 24x13 direct with registers capped for 4 waves per SIMD (two workgroups per CU; 24x13
+// is the single-grid FP32 kernel's shape).
 const BatchTileCfg kBatchCfgs[kNumBatchCfgs] = {
     {32, 8, 512, false, 1}, {32, 8, 256, false, 1}, {32, 16, 512, false, 1}, {32, 16, 256, false, 1},
     {64, 8, 512, false, 1}, {16, 16, 256, false, 1}, {32, 8, 512, true, 1},   {32, 8, 256, true, 1},
     {32, 16, 512, true, 1}, {32, 16, 256, true, 1},  {64, 8, 512, true, 1},   {16, 16, 256, true, 1},
-    {32, 8, 512, true, 4},
+    {32, 8, 512, true, 4},  {24, 13, 512, true, 4},
 };
 
 #define AF_BATCH_SWITCH(F, ...)                                   \
     {                                                             \
         if (cfg == 12) return F<32, 8, 512, 4>(true, __VA_ARGS__); \
+        if (cfg == 13) return F<24, 13, 512, 4>(true, __VA_ARGS__); \
         const bool direct = cfg >= 6;                             \
         switch (cfg % 6) {                                        \
             case 0: return F<32, 8, 512>(direct, __VA_ARGS__);    \

@@ -57,7 +57,7 @@ def single(torch_dev, P, x, dt, n):
     return y
 
 
-@pytest.mark.parametrize("cfg", list(range(13)))
+@pytest.mark.parametrize("cfg", list(range(14)))
 def test_batch_tile_cfg_matches_single_grid(torch_dev, cfg, monkeypatch):
     torch, dev = torch_dev
     from paper_2605_12915_amd.stepper import Batch
