@@ -53,16 +53,6 @@ struct AdjNodes {
     }
 };
 
-struct AdjInc {
-    const double* d;    // 12 planes of one duration
-    int nx, ny;
-    __device__ __forceinline__ double inc(int fam, int i, int j, int var) const {
-        i = (i < 0) ? i + nx : (i >= nx ? i - nx : i);
-        j = (j < 0) ? j + ny : (j >= ny ? j - ny : j);
-        return d[(size_t)(fam * 3 + var) * nx * ny + (size_t)j * nx + i];
-    }
-};
-
 // Scatter target of the reverse sweep: an LDS window of NPL planes over node-cells
 // [ri0, ri0 + RX) x [rj0, rj0 + RY) (unwrapped indices; the flush wraps them).
 // Planes: 0..11 point values (family * 4 + (rho, u, v, p)), 12..15 recovered
@@ -71,8 +61,15 @@ template <int NPL, int RX, int RY>
 struct LdsWin {
     double* a;
     int ri0, rj0;
+    static constexpr int kRX = RX, kPlane = RX * RY;
     __device__ __forceinline__ void add(int pl, int i, int j, double v) const {
         atomicAdd(a + (pl * RY + (j - rj0)) * RX + (i - ri0), v);
+    }
+    // offset of node-cell (i, j) within a plane; addb adds to plane pl at that offset
+    // plus a small constant one (so that every add of one cell's nodes shares a base)
+    __device__ __forceinline__ int base(int i, int j) const { return (j - rj0) * RX + (i - ri0); }
+    __device__ __forceinline__ void addb(int pl, int b, int off, double v) const {
+        atomicAdd(a + b + (pl * kPlane + off), v);
     }
     // add g = (d rho, d u, d v, d p) to node fam of cell (i, j)
     __device__ __forceinline__ void node(int fam, int i, int j, const double g[4]) const {
@@ -92,6 +89,22 @@ struct LdsWin {
 };
 
 struct PlaneList { double* p[40]; };
+
+// The forward state of a block, staged in LDS over the node-cells of its scatter
+// window with the window's plane numbering: point values (0..11), recovered centres
+// (12..15), increments of both durations (16..39).
+template <int RX, int RY>
+struct StageWin {
+    const double* a;
+    int ri0, rj0;
+    static constexpr int kRX = RX, kPlane = RX * RY;
+    __device__ __forceinline__ int base(int i, int j) const { return (j - rj0) * RX + (i - ri0); }
+    __device__ __forceinline__ double at(int pl, int b, int off) const { return a[b + (pl * kPlane + off)]; }
+    __device__ __forceinline__ Prim<double> node(int fam, int b) const {
+        const int pl = fam == F_C ? 12 : 4 * fam;
+        return {at(pl, b, 0), at(pl + 1, b, 0), at(pl + 2, b, 0), at(pl + 3, b, 0)};
+    }
+};
 
 // Add an LDS window to its global planes (periodic wrap), one atomic per nonzero entry.
 template <int NPL, int RX, int RY>
@@ -113,6 +126,21 @@ __device__ __forceinline__ void node_of(int a, int b, int ci, int cj, int& fam, 
     fam = fa[a][b];
     i = ci + (a == 2 ? 1 : 0);
     j = cj + (b == 2 ? 1 : 0);
+}
+
+// Family of node [a][b] of a cell, the node-cell (dx, dy) of the cell's 2x2 block of
+// node-cells that holds it, and its first plane in the scatter window (point values
+// fam * 4, centre 12).
+__device__ __forceinline__ constexpr int fam_of(int a, int b) {
+    return (a == 1 && b == 1) ? F_C : (a == 1 ? F_EH : (b == 1 ? F_EV : F_V));
+}
+__device__ __forceinline__ constexpr int win_plane(int fam) { return fam == F_C ? 12 : 4 * fam; }
+
+// Periodic index: one shift (offsets of at most one grid length) or a modulo.
+__device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+__device__ __forceinline__ int wrap_any(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
 }
 
 __device__ __forceinline__ void lagr(double s, double l[3], double dl[3]) {
@@ -144,16 +172,19 @@ __device__ __forceinline__ void flux_y_T(const Prim<double>& w, double gamma, co
 }
 
 // Transposed transported point update (scheme 0) of target FAM at (i, j) for the
-// duration tau = lam h; lw = adjoint of the new point value.
+// duration tau = lam h; WP = the target's time-n value.
 // The forward value w is recomputed here and its cotangent formed from the flux
 // cotangents: lw = ws * (dF/dW)^T nuF + ws * (dG/dW)^T nuG (+ extra: the cotangent
-// of the new point value itself, for the full step).
-template <int FAM, class O_>
-__device__ void point_update_adj(const AdjNodes& A, const AdjInc& D, const O_& O, int t, int i, int j,
+// of the new point value itself, for the full step).  The contributions to the
+// target's own node (through the first foot position) are added to gself, those to
+// the nodes of the two foot cells go to the window, one base offset per cell.
+template <int FAM, class S_, class O_>
+__device__ void point_update_adj(const S_& S, const O_& O, int t, int i, int j, const Prim<double>& WP,
                                  double gamma, double lam, const double nuF[4], const double nuG[4], double ws,
-                                 const double* extra) {
+                                 const double* extra, double gself[4]) {
     const double ox = FamOffset<FAM>::ox, oy = FamOffset<FAM>::oy;
-    const Prim<double> WP = A.node(FAM, i, j);
+    constexpr int RX = O_::kRX;
+    static_assert(S_::kRX == O_::kRX && S_::kPlane == O_::kPlane, "staged state and window share a layout");
     unsigned st = 0;
     // ---- forward recomputation ----
     int cx1, cy1, cx2, cy2;
@@ -163,49 +194,51 @@ __device__ void point_update_adj(const AdjNodes& A, const AdjInc& D, const O_& O
     double lx1[3], dlx1[3], ly1[3], dly1[3];
     lagr(xi1, lx1, dlx1);
     lagr(eta1, ly1, dly1);
-    Prim<double> n1[3][3];
-    cell_nodes<double>(A, i + cx1, j + cy1, n1);
     double u1 = 0.0, v1 = 0.0, du1x = 0.0, du1y = 0.0, dv1x = 0.0, dv1y = 0.0;
+    const int wb1 = O.base(i + cx1, j + cy1);
+    {
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            u1 += lx1[a] * ly1[b] * n1[a][b].u;
-            v1 += lx1[a] * ly1[b] * n1[a][b].v;
-            du1x += dlx1[a] * ly1[b] * n1[a][b].u;
-            du1y += lx1[a] * dly1[b] * n1[a][b].u;
-            dv1x += dlx1[a] * ly1[b] * n1[a][b].v;
-            dv1y += lx1[a] * dly1[b] * n1[a][b].v;
-        }
+            for (int b = 0; b < 3; ++b) {
+                const int f = fam_of(a, b), off = (b == 2 ? RX : 0) + (a == 2 ? 1 : 0);
+                const double nu_ = S.at(win_plane(f) + 1, wb1, off), nv_ = S.at(win_plane(f) + 2, wb1, off);
+                u1 += lx1[a] * ly1[b] * nu_;
+                v1 += lx1[a] * ly1[b] * nv_;
+                du1x += dlx1[a] * ly1[b] * nu_;
+                du1y += lx1[a] * dly1[b] * nu_;
+                dv1x += dlx1[a] * ly1[b] * nv_;
+                dv1y += lx1[a] * dly1[b] * nv_;
+            }
+    }
     locate(ox - lam * u1, ox, cx2, xi2, st);
     locate(oy - lam * v1, oy, cy2, eta2, st);
     double lx2[3], dlx2[3], ly2[3], dly2[3];
     lagr(xi2, lx2, dlx2);
     lagr(eta2, ly2, dly2);
     const int ci = i + cx2, cj = j + cy2;
-    Prim<double> n2[3][3];
-    cell_nodes<double>(A, ci, cj, n2);
     double Wf[4] = {0, 0, 0, 0}, dWx[4] = {0, 0, 0, 0}, dWy[4] = {0, 0, 0, 0};
     double Df[3] = {0, 0, 0}, dDx[3] = {0, 0, 0}, dDy[3] = {0, 0, 0};
-    double dn[3][3][3];
+    const int wb2 = O.base(ci, cj);
+    {
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const double w = lx2[a] * ly2[b], wx = dlx2[a] * ly2[b], wy = lx2[a] * dly2[b];
-            const double f[4] = {n2[a][b].r, n2[a][b].u, n2[a][b].v, n2[a][b].p};
+            for (int b = 0; b < 3; ++b) {
+                const double w = lx2[a] * ly2[b], wx = dlx2[a] * ly2[b], wy = lx2[a] * dly2[b];
+                const int f = fam_of(a, b), off = (b == 2 ? RX : 0) + (a == 2 ? 1 : 0);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) { Wf[q] += w * f[q]; dWx[q] += wx * f[q]; dWy[q] += wy * f[q]; }
-            int fam, ii, jj;
-            node_of(a, b, ci, cj, fam, ii, jj);
+                for (int q = 0; q < 4; ++q) {
+                    const double v = S.at(win_plane(f) + q, wb2, off);
+                    Wf[q] += w * v; dWx[q] += wx * v; dWy[q] += wy * v;
+                }
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                dn[a][b][q] = D.inc(fam, ii, jj, q);
-                Df[q] += w * dn[a][b][q];
-                dDx[q] += wx * dn[a][b][q];
-                dDy[q] += wy * dn[a][b][q];
+                for (int q = 0; q < 3; ++q) {
+                    const double v = S.at(16 + t * 12 + f * 3 + q, wb2, off);
+                    Df[q] += w * v; dDx[q] += wx * v; dDy[q] += wy * v;
+                }
             }
-        }
+    }
     // ---- reverse ----
     // compose: rho = rho_f + dp rho_f / (gamma p_f), u = u_f + du, v = v_f + dv, p = p_f + dp
     const double qinv = 1.0 / (gamma * Wf[3]);
@@ -236,18 +269,19 @@ __device__ void point_update_adj(const AdjNodes& A, const AdjInc& D, const O_& O
     lDf[1] = lw[2];
     lDf[2] = lw[3] + lw[0] * Wf[0] * qinv;
     // Q2 values at the foot -> nodes of the foot cell
+    {
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const double w = lx2[a] * ly2[b];
-            int fam, ii, jj;
-            node_of(a, b, ci, cj, fam, ii, jj);
-            const double g[4] = {w * lWf[0], w * lWf[1], w * lWf[2], w * lWf[3]};
-            O.node(fam, ii, jj, g);
-            const double gd[3] = {w * lDf[0], w * lDf[1], w * lDf[2]};
-            O.inc(t, fam, ii, jj, gd);
-        }
+            for (int b = 0; b < 3; ++b) {
+                const double w = lx2[a] * ly2[b];
+                const int f = fam_of(a, b), off = (b == 2 ? RX : 0) + (a == 2 ? 1 : 0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) O.addb(win_plane(f) + q, wb2, off, w * lWf[q]);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) O.addb(16 + t * 12 + f * 3 + q, wb2, off, w * lDf[q]);
+            }
+    }
     // foot position: xi2 = 2 (off - floor(off)) - 1, off = ox - lam u1
     double lxi2 = 0.0, leta2 = 0.0;
 #pragma unroll
@@ -256,19 +290,20 @@ __device__ void point_update_adj(const AdjNodes& A, const AdjInc& D, const O_& O
     for (int q = 0; q < 3; ++q) { lxi2 += lDf[q] * dDx[q]; leta2 += lDf[q] * dDy[q]; }
     const double lu1 = -2.0 * lam * lxi2, lv1 = -2.0 * lam * leta2;
     // first stage: u1 = Q2(u) at (xi1, eta1)
+    {
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const double w = lx1[a] * ly1[b];
-            int fam, ii, jj;
-            node_of(a, b, i + cx1, j + cy1, fam, ii, jj);
-            const double g[4] = {0.0, w * lu1, w * lv1, 0.0};
-            O.node(fam, ii, jj, g);
-        }
+            for (int b = 0; b < 3; ++b) {
+                const double w = lx1[a] * ly1[b];
+                const int f = fam_of(a, b), off = (b == 2 ? RX : 0) + (a == 2 ? 1 : 0);
+                O.addb(win_plane(f) + 1, wb1, off, w * lu1);
+                O.addb(win_plane(f) + 2, wb1, off, w * lv1);
+            }
+    }
     const double lxi1 = lu1 * du1x + lv1 * dv1x, leta1 = lu1 * du1y + lv1 * dv1y;
-    const double gP[4] = {0.0, -2.0 * lam * lxi1, -2.0 * lam * leta1, 0.0};
-    O.node(FAM, i, j, gP);
+    gself[1] += -2.0 * lam * lxi1;
+    gself[2] += -2.0 * lam * leta1;
 }
 
 __global__ void __launch_bounds__(256) k_adj_zero_list(PlaneList L, int nplanes, size_t N) {
@@ -280,16 +315,13 @@ __global__ void __launch_bounds__(256) k_adj_zero_list(PlaneList L, int nplanes,
 // Reverse sweep of one target (family FAM of node-cell (i, j)): the adjoints of the
 // edge fluxes it feeds, from the averages' cotangents, then of its three time levels
 // (w^n directly, w^{n+1/2} and w^{n+1} through the transposed point update).
-template <int FAM, class O_>
-__device__ void point_adj_target(const StatePtrs<double>& prim, const double* C, const double* Dfwd,
-                                 const StatePtrs<double>& cot1, const O_& O, int nx, int ny, int i, int j,
-                                 double gamma, double lam0, double lam1) {
-    AdjNodes A{{}, C, nx, ny};
-#pragma unroll
-    for (int k = 0; k < 16; ++k) A.s[k] = prim.p[k];
-    const size_t N = (size_t)nx * ny;
-    AdjInc D0{Dfwd, nx, ny}, D1{Dfwd + 12 * N, nx, ny};
-    auto lU = [&](int a, int b, int k) -> double { return cot1.p[k][A.idx(a, b)]; };
+template <int FAM, class S_, class O_>
+__device__ void point_adj_target(const S_& S, const StatePtrs<double>& cot1, const O_& O, int nx, int ny, int i,
+                                 int j, double gamma, double lam0, double lam1) {
+    const int im = wrap1(i - 1, nx), jm = wrap1(j - 1, ny);
+    auto lU = [&](int a, int b, int k) -> double {
+        return cot1.p[k][(size_t)(b == j ? j : jm) * nx + (a == i ? i : im)];
+    };
     // cotangents of the time-integrated edge fluxes at this node: F at V and Ev, G at
     // V and Eh; spatial Simpson weights 1/6 (V, two edges each) and 4/6 (edge midpoints)
     double nuF[4] = {0, 0, 0, 0}, nuG[4] = {0, 0, 0, 0};
@@ -309,9 +341,11 @@ __device__ void point_adj_target(const StatePtrs<double>& prim, const double* C,
         }
     }
     // time level n (time-Simpson weight 1/6): the node itself
+    const int wb = O.base(i, j);
+    const Prim<double> w0 = S.node(FAM, wb);
+    double g[4] = {0.0, 0.0, 0.0, 0.0};
     {
-        const Prim<double> w0 = A.node(FAM, i, j);
-        double g[4] = {0.0, 0.0, 0.0, 0.0}, nu[4];
+        double nu[4];
         if constexpr (FAM != F_EH) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) nu[k] = nuF[k] * (1.0 / 6.0);
@@ -322,37 +356,60 @@ __device__ void point_adj_target(const StatePtrs<double>& prim, const double* C,
             for (int k = 0; k < 4; ++k) nu[k] = nuG[k] * (1.0 / 6.0);
             flux_y_T(w0, gamma, nu, g);
         }
-        O.node(FAM, i, j, g);
     }
     // n + 1/2 (weight 4/6) and n + 1 (weight 1/6; also an output of the step)
-    point_update_adj<FAM>(A, D0, O, 0, i, j, gamma, lam0, nuF, nuG, 4.0 / 6.0, nullptr);
-    const size_t c = A.idx(i, j);
+    point_update_adj<FAM>(S, O, 0, i, j, w0, gamma, lam0, nuF, nuG, 4.0 / 6.0, nullptr, g);
+    const size_t c = (size_t)j * nx + i;
     const double extra[4] = {cot1.p[4 + 4 * FAM][c], cot1.p[5 + 4 * FAM][c], cot1.p[6 + 4 * FAM][c],
                              cot1.p[7 + 4 * FAM][c]};
-    point_update_adj<FAM>(A, D1, O, 1, i, j, gamma, lam1, nuF, nuG, 1.0 / 6.0, extra);
+    point_update_adj<FAM>(S, O, 1, i, j, w0, gamma, lam1, nuF, nuG, 1.0 / 6.0, extra, g);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) O.addb(win_plane(FAM) + q, wb, 0, g[q]);
 }
 
 // Reverse of the point update, fluxes and average update for a BX x BY block of
 // cells, one thread per (cell, target family).  Feet stay within one cell (guarded),
-// so every contribution lands on node-cells [-1, B + 2) of the block: the LDS window.
+// so every read of the forward state and every contribution lies in node-cells
+// [-1, B + 2) of the block: the block stages the forward state of that window in LDS
+// (each thread loads all 40 planes of one node-cell at once) and accumulates into an
+// LDS window of the same shape.
 constexpr int kPBX = 16, kPBY = 8, kPNT = 3 * kPBX * kPBY;
-constexpr int kPRX = kPBX + 3, kPRY = kPBY + 3;
+constexpr int kPRX = kPBX + 3, kPRY = kPBY + 3, kPWin = kPRX * kPRY;
 using PointWin = LdsWin<40, kPRX, kPRY>;
+using PointStage = StageWin<kPRX, kPRY>;
+constexpr size_t kPointLds = sizeof(double) * 2 * 40 * kPWin;   // staged state + accumulators
+static_assert(kPWin <= kPNT, "one staging round");
 
 __global__ void __launch_bounds__(kPNT) k_adj_points(StatePtrs<double> prim, const double* C, const double* Dfwd,
                                                      StatePtrs<double> cot1, PlaneList G, int nx, int ny,
                                                      double gamma, double lam0, double lam1) {
     extern __shared__ __align__(16) unsigned char smem[];
+    double* stage = reinterpret_cast<double*>(smem);   // [40][RY][RX]
     const int i0 = blockIdx.x * kPBX, j0 = blockIdx.y * kPBY;
-    const PointWin O{reinterpret_cast<double*>(smem), i0 - 1, j0 - 1};
+    const PointWin O{stage + 40 * kPWin, i0 - 1, j0 - 1};
     O.zero();
+    if (threadIdx.x < kPWin) {
+        const int e = threadIdx.x;
+        const int i = wrap_any(i0 - 1 + e % kPRX, nx), j = wrap_any(j0 - 1 + e / kPRX, ny);
+        const size_t N = (size_t)nx * ny, k = (size_t)j * nx + i;
+        double v[40];
+#pragma unroll
+        for (int pl = 0; pl < 12; ++pl) v[pl] = prim.p[4 + pl][k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[12 + q] = C[q * N + k];
+#pragma unroll
+        for (int q = 0; q < 24; ++q) v[16 + q] = Dfwd[q * N + k];
+#pragma unroll
+        for (int pl = 0; pl < 40; ++pl) stage[pl * kPWin + e] = v[pl];
+    }
     __syncthreads();
+    const PointStage S{stage, i0 - 1, j0 - 1};
     const int cell = (int)threadIdx.x % (kPBX * kPBY), fam = (int)threadIdx.x / (kPBX * kPBY);   // wave-uniform
     const int i = i0 + cell % kPBX, j = j0 + cell / kPBX;
     if (i < nx && j < ny) {
-        if (fam == F_V) point_adj_target<F_V>(prim, C, Dfwd, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
-        else if (fam == F_EV) point_adj_target<F_EV>(prim, C, Dfwd, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
-        else point_adj_target<F_EH>(prim, C, Dfwd, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
+        if (fam == F_V) point_adj_target<F_V>(S, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
+        else if (fam == F_EV) point_adj_target<F_EV>(S, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
+        else point_adj_target<F_EH>(S, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
     }
     __syncthreads();
     flush_window(O, G, nx, ny);
@@ -608,7 +665,7 @@ hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1_[16], vo
     const double lam1 = a.dt / a.h, lam0 = 0.5 * lam1;
     if (a.ev_begin) (void)hipEventRecord(a.ev_begin, a.stream);
     {
-        const size_t lds = sizeof(double) * 40 * kPRX * kPRY;   // allowed by prepare_adjoint_f64
+        const size_t lds = kPointLds;   // allowed by prepare_adjoint_f64
         dim3 grd((a.nx + kPBX - 1) / kPBX, (a.ny + kPBY - 1) / kPBY);
         hipLaunchKernelGGL(k_adj_points, grd, dim3(kPNT), lds, a.stream, prim, C, Dfwd, cot1, L, a.nx, a.ny,
                            a.gamma, lam0, lam1);
@@ -629,7 +686,7 @@ hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1_[16], vo
 
 hipError_t prepare_adjoint_f64() {
     return hipFuncSetAttribute((const void*)k_adj_points, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(sizeof(double) * 40 * kPRX * kPRY));
+                               (int)kPointLds);
 }
 
 size_t scratch_bytes_adjoint_f64(int nx, int ny) { return (size_t)nx * ny * (4 + 24 + 4 + 24) * sizeof(double); }
