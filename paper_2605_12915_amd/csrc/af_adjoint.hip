@@ -306,10 +306,122 @@ __device__ void point_update_adj(const S_& S, const O_& O, int t, int i, int j, 
     gself[2] += -2.0 * lam * leta1;
 }
 
-__global__ void __launch_bounds__(256) k_adj_zero_list(PlaneList L, int nplanes, size_t N) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < N; k += stride)
-        for (int p = 0; p < nplanes; ++p) L.p[p][k] = 0.0;
+// Forward intermediates of a TX x TY tile, recomputed from state_n for the reverse
+// sweep: the tile's primitive node values (node-cells [-1, T+1)) and recovered centres
+// (cells [-1, T)) staged in LDS, then the increments of both durations at the tile's
+// own node-cells (every wedge of a node-cell in [0, T) lies in cells [-1, T)).  Writes
+// W^C of the tile's cells and the 24 increment planes, and zeroes the tile's cells of
+// the planes the reverse sweep accumulates into.
+template <int TX, int TY>
+struct IntTile {
+    static constexpr int PX = TX + 2, PY = TY + 2, CX = TX + 1, CY = TY + 1;
+    double P[12][PY][PX];
+    double C[4][CY][CX];
+};
+
+template <int TX, int TY>
+struct IntAcc {
+    const IntTile<TX, TY>* t;
+    __device__ __forceinline__ Prim<double> node(int fam, int x, int y) const {
+        if (fam == F_C) return {t->C[0][y + 1][x + 1], t->C[1][y + 1][x + 1], t->C[2][y + 1][x + 1], t->C[3][y + 1][x + 1]};
+        const int b = 4 * fam;
+        return {t->P[b][y + 1][x + 1], t->P[b + 1][y + 1][x + 1], t->P[b + 2][y + 1][x + 1], t->P[b + 3][y + 1][x + 1]};
+    }
+};
+
+constexpr int kFBX = 32, kFBY = 8, kFNT = kFBX * kFBY;
+using FwdTile = IntTile<kFBX, kFBY>;
+
+// two workgroups per CU (256 registers per lane)
+__global__ void __launch_bounds__(kFNT, 2) k_adj_fwd(StatePtrs<double> prim, double* C, double* D, PlaneList Z,
+                                                     int nzero, int nx, int ny, double gamma, double lam0,
+                                                     double lam1, unsigned* status) {
+    __shared__ FwdTile L;
+    const int i0 = blockIdx.x * kFBX, j0 = blockIdx.y * kFBY, tid = threadIdx.x;
+    const size_t N = (size_t)nx * ny;
+    const int ox = tid % kFBX, oy = tid / kFBX;
+    const bool own = i0 + ox < nx && j0 + oy < ny;
+    const size_t g = own ? (size_t)(j0 + oy) * nx + (i0 + ox) : 0;
+    unsigned st = 0;
+    // stage primitives: all loads of a thread's rounds are issued before its stores
+    {
+        constexpr int NP = FwdTile::PX * FwdTile::PY, R = (NP + kFNT - 1) / kFNT;
+        double v[R][12];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = r * kFNT + tid;
+            if (e < NP) {
+                const size_t k = (size_t)wrap_any(j0 - 1 + e / FwdTile::PX, ny) * nx + wrap_any(i0 - 1 + e % FwdTile::PX, nx);
+#pragma unroll
+                for (int q = 0; q < 12; ++q) v[r][q] = prim.p[4 + q][k];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = r * kFNT + tid;
+            if (e < NP)
+#pragma unroll
+                for (int q = 0; q < 12; ++q) L.P[q][e / FwdTile::PX][e % FwdTile::PX] = v[r][q];
+        }
+    }
+    if (own)
+        for (int q = 0; q < nzero; ++q) Z.p[q][g] = 0.0;
+    __syncthreads();
+    // recovered centres of cells [-1, T)
+    {
+        const IntAcc<kFBX, kFBY> A{&L};
+        for (int e = tid; e < FwdTile::CX * FwdTile::CY; e += kFNT) {
+            const int x = e % FwdTile::CX - 1, y = e / FwdTile::CX - 1;
+            const size_t k = (size_t)wrap_any(j0 + y, ny) * nx + wrap_any(i0 + x, nx);
+            const double Ub[4] = {prim.p[0][k], prim.p[1][k], prim.p[2][k], prim.p[3][k]};
+            const Prim<double> w = recover_centre(Ub, A.node(F_V, x, y), A.node(F_V, x + 1, y), A.node(F_V, x, y + 1),
+                                                  A.node(F_V, x + 1, y + 1), A.node(F_EH, x, y), A.node(F_EH, x, y + 1),
+                                                  A.node(F_EV, x, y), A.node(F_EV, x + 1, y), gamma);
+            L.C[0][y + 1][x + 1] = w.r;
+            L.C[1][y + 1][x + 1] = w.u;
+            L.C[2][y + 1][x + 1] = w.v;
+            L.C[3][y + 1][x + 1] = w.p;
+            if (x >= 0 && y >= 0 && i0 + x < nx && j0 + y < ny) {
+                const size_t c = (size_t)(j0 + y) * nx + (i0 + x);
+                C[c] = w.r;
+                C[N + c] = w.u;
+                C[2 * N + c] = w.v;
+                C[3 * N + c] = w.p;
+                if (!(w.r > 0.0) || !(w.p > 0.0)) st |= SB_NONPHYS;
+            }
+        }
+    }
+    __syncthreads();
+    // increments of the tile's own node-cells
+    if (own) {
+        const IntAcc<kFBX, kFBY> A{&L};
+        const PolAbs<double> pol{gamma, 1.0 / (gamma - 1.0)};
+        double d[2][3];
+        node_increments<F_V>(A, ox, oy, pol, lam0, lam1, d, st);
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int v = 0; v < 3; ++v) D[(size_t)(t * 12 + 0 * 3 + v) * N + g] = d[t][v];
+        __builtin_amdgcn_sched_barrier(0);   // one family at a time: interleaving them spills
+        node_increments<F_EV>(A, ox, oy, pol, lam0, lam1, d, st);
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int v = 0; v < 3; ++v) D[(size_t)(t * 12 + 1 * 3 + v) * N + g] = d[t][v];
+        __builtin_amdgcn_sched_barrier(0);
+        node_increments<F_EH>(A, ox, oy, pol, lam0, lam1, d, st);
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int v = 0; v < 3; ++v) D[(size_t)(t * 12 + 2 * 3 + v) * N + g] = d[t][v];
+        __builtin_amdgcn_sched_barrier(0);
+        node_increments<F_C>(A, ox, oy, pol, lam0, lam1, d, st);
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int v = 0; v < 3; ++v) D[(size_t)(t * 12 + 3 * 3 + v) * N + g] = d[t][v];
+    }
+    if (st) atomicOr(status, st);
 }
 
 // Reverse sweep of one target (family FAM of node-cell (i, j)): the adjoints of the
@@ -653,16 +765,18 @@ hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1_[16], vo
         cot1.p[k] = (double*)cot1_[k];
         cot0.p[k] = (double*)cot0_[k];
     }
-    hipError_t e = launch_intermediates_f64(a, C, Dfwd);
-    if (e != hipSuccess) return e;
     PlaneList L;
     int np = 0;
     for (int k = 4; k < 16; ++k) L.p[np++] = cot0.p[k];
     for (int k = 0; k < 4; ++k) L.p[np++] = lC + k * N;
     for (int k = 0; k < 24; ++k) L.p[np++] = lD + k * N;
-    hipLaunchKernelGGL(k_adj_zero_list, dim3(1024), dim3(256), 0, a.stream, L, np, N);
-    // L now lists the window planes in LdsWin order: point values, centres, increments
+    // L lists the window planes in LdsWin order: point values, centres, increments
     const double lam1 = a.dt / a.h, lam0 = 0.5 * lam1;
+    {
+        dim3 grd((a.nx + kFBX - 1) / kFBX, (a.ny + kFBY - 1) / kFBY);
+        hipLaunchKernelGGL(k_adj_fwd, grd, dim3(kFNT), 0, a.stream, prim, C, Dfwd, L, np, a.nx, a.ny, a.gamma, lam0,
+                           lam1, a.status);
+    }
     if (a.ev_begin) (void)hipEventRecord(a.ev_begin, a.stream);
     {
         const size_t lds = kPointLds;   // allowed by prepare_adjoint_f64

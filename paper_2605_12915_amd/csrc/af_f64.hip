@@ -205,16 +205,6 @@ hipError_t launch_step_multi_f64(const StepArgs& a) {
     return hipGetLastError();
 }
 
-hipError_t launch_intermediates_f64(const StepArgs& a, double* C, double* D) {
-    dim3 blk(64, 4), grd((a.nx + 63) / 64, (a.ny + 3) / 4);
-    StatePtrs<double> in;
-    for (int k = 0; k < 16; ++k) in.p[k] = (double*)a.in[k];
-    const double lam1 = a.dt / a.h, lam0 = 0.5 * lam1;
-    hipLaunchKernelGGL(k_centre, grd, blk, 0, a.stream, in, C, a.nx, a.ny, a.gamma, a.status);
-    hipLaunchKernelGGL(k_incr, grd, blk, 0, a.stream, in, C, D, a.nx, a.ny, a.gamma, lam0, lam1, a.status);
-    return hipGetLastError();
-}
-
 size_t scratch_bytes_multi_f64(int nx, int ny) { return (size_t)nx * ny * (4 + 24 + 12) * sizeof(double); }
 
 }  // namespace af

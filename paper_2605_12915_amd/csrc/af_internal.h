@@ -36,7 +36,6 @@ DiagBg diag_bg(bool f32, const double bg[4], double gamma);
 hipError_t launch_diag_final(const double* partials, int n, double* out9, hipStream_t stream);
 
 hipError_t launch_step_multi_f64(const StepArgs& a);
-hipError_t launch_intermediates_f64(const StepArgs& a, double* C, double* D);
 hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1[16], void* const cot0[16]);
 size_t scratch_bytes_adjoint_f64(int nx, int ny);
 hipError_t launch_step_fused_f64(const StepArgs& a);
