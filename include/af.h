@@ -107,8 +107,9 @@ af_status af_step_out(af_ctx* ctx, const af_state* in, af_state* out, double dt)
  * (synchronises the stream).  *status receives AF_OK or the first error class. */
 af_status af_read_status(af_ctx* ctx, af_status* status);
 
-/* Reverse-mode derivative of one step (AF_F64 only): cot_n = (d step / d state_n)^T
- * cot_np1 at fixed dt, where step is the map of af_step_out.  primal_n: the state the
+/* Reverse-mode derivative of one step (AF_F64 only; either point update, TAI or
+ * AF_SCHEME_RB): cot_n = (d step / d state_n)^T cot_np1 at fixed dt, where step is the
+ * map of af_step_out.  primal_n: the state the
  * step was taken from; cot_np1: cotangent of the step's output; cot_n: overwritten
  * (not accumulated).  All three are caller-owned device states of doubles. */
 af_status af_step_adjoint(af_ctx* ctx, const af_state* primal_n, const af_state* cot_np1,
@@ -125,8 +126,8 @@ af_status af_diagnostics(af_ctx* ctx, const af_state* s, double dt, af_diag* out
 af_status af_time_steps(af_ctx* ctx, const af_state* s, double dt, int32_t nsteps,
                         double* total_ms, double* kernel_ms);
 
-/* Batching form.  n grids (each described by its own af_config; all AF_F32, TAI
- * scheme) stepped together: every step is ONE kernel launch over the list of
+/* Batching form.  n grids (each described by its own af_config; all AF_F32, all with
+ * the same point update: TAI, or AF_SCHEME_RB for every grid) stepped together: every step is ONE kernel launch over the list of
  * (grid, tile) work items of the whole batch, and af_step_batch replays nsteps such
  * launches captured in a hipGraph (built on first use for each nsteps and kept; at
  * most 16 distinct nsteps are kept at a time).  The tile shape is chosen by an
@@ -145,8 +146,8 @@ af_status af_time_steps(af_ctx* ctx, const af_state* s, double dt, int32_t nstep
  * it. */
 af_status af_init_batch(const af_config* cfgs, int32_t n, void* hip_stream, af_ctx** out);
 /* (af_init_batch errors: AF_ERR_ARG for n outside 1..4096 or a config af_init would
- * reject; AF_ERR_UNSUPPORTED for a config that is not AF_F32 or asks for
- * AF_SCHEME_RB.  Configs are checked before any HIP call.) */
+ * reject; AF_ERR_UNSUPPORTED for a config that is not AF_F32, or whose AF_SCHEME_RB
+ * flag differs from the first config's.  Configs are checked before any HIP call.) */
 
 /* Advance every grid q of a batch context by nsteps (1..65536) steps of size dts[q]
  * in place; states[q] are caller-owned float perturbation planes (layout as above).

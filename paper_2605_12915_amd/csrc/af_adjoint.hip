@@ -171,14 +171,16 @@ __device__ __forceinline__ void flux_y_T(const Prim<double>& w, double gamma, co
     g[3] += nu[2] + nu[3] * w.v * gamma / (gamma - 1.0);
 }
 
-// Transposed transported point update (scheme 0) of target FAM at (i, j) for the
-// duration tau = lam h; WP = the target's time-n value.
+// Transposed point update of target FAM at (i, j) for the duration tau = lam h;
+// WP = the target's time-n value.  SCHEME 0: transported update (the increments are
+// interpolated at the foot, the density closure uses c^2 at the foot); SCHEME 1:
+// additive update (the target's own increments, c^2 frozen at the target).
 // The forward value w is recomputed here and its cotangent formed from the flux
 // cotangents: lw = ws * (dF/dW)^T nuF + ws * (dG/dW)^T nuG (+ extra: the cotangent
 // of the new point value itself, for the full step).  The contributions to the
 // target's own node (through the first foot position) are added to gself, those to
 // the nodes of the two foot cells go to the window, one base offset per cell.
-template <int FAM, class S_, class O_>
+template <int FAM, int SCHEME, class S_, class O_>
 __device__ void point_update_adj(const S_& S, const O_& O, int t, int i, int j, const Prim<double>& WP,
                                  double gamma, double lam, const double nuF[4], const double nuG[4], double ws,
                                  const double* extra, double gself[4]) {
@@ -232,19 +234,28 @@ __device__ void point_update_adj(const S_& S, const O_& O, int t, int i, int j, 
                     const double v = S.at(win_plane(f) + q, wb2, off);
                     Wf[q] += w * v; dWx[q] += wx * v; dWy[q] += wy * v;
                 }
+                if constexpr (SCHEME == 0) {
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    const double v = S.at(16 + t * 12 + f * 3 + q, wb2, off);
-                    Df[q] += w * v; dDx[q] += wx * v; dDy[q] += wy * v;
+                    for (int q = 0; q < 3; ++q) {
+                        const double v = S.at(16 + t * 12 + f * 3 + q, wb2, off);
+                        Df[q] += w * v; dDx[q] += wx * v; dDy[q] += wy * v;
+                    }
                 }
             }
     }
+    const int wbP = O.base(i, j);
+    if constexpr (SCHEME == 1) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) Df[q] = S.at(16 + t * 12 + FAM * 3 + q, wbP, 0);
+    }
     // ---- reverse ----
-    // compose: rho = rho_f + dp rho_f / (gamma p_f), u = u_f + du, v = v_f + dv, p = p_f + dp
-    const double qinv = 1.0 / (gamma * Wf[3]);
+    // compose: rho = rho_f + dp rho_K / (gamma p_K), u = u_f + du, v = v_f + dv, p = p_f + dp,
+    // with K the foot (SCHEME 0) or the target (SCHEME 1)
+    const double rK = SCHEME == 0 ? Wf[0] : WP.r, pK = SCHEME == 0 ? Wf[3] : WP.p;
+    const double qinv = 1.0 / (gamma * pK);
     double lw[4] = {0.0, 0.0, 0.0, 0.0};
     {
-        const Prim<double> w{Wf[0] + Df[2] * (Wf[0] * qinv), Wf[1] + Df[0], Wf[2] + Df[1], Wf[3] + Df[2]};
+        const Prim<double> w{Wf[0] + Df[2] * (rK * qinv), Wf[1] + Df[0], Wf[2] + Df[1], Wf[3] + Df[2]};
         double nu[4];
         if constexpr (FAM != F_EH) {
 #pragma unroll
@@ -261,13 +272,23 @@ __device__ void point_update_adj(const S_& S, const O_& O, int t, int i, int j, 
             for (int k = 0; k < 4; ++k) lw[k] += extra[k];
     }
     double lWf[4], lDf[3];
-    lWf[0] = lw[0] * (1.0 + Df[2] * qinv);
-    lWf[1] = lw[1];
-    lWf[2] = lw[2];
-    lWf[3] = lw[3] - lw[0] * Df[2] * Wf[0] * qinv / Wf[3];
     lDf[0] = lw[1];
     lDf[1] = lw[2];
-    lDf[2] = lw[3] + lw[0] * Wf[0] * qinv;
+    lDf[2] = lw[3] + lw[0] * rK * qinv;
+    lWf[1] = lw[1];
+    lWf[2] = lw[2];
+    if constexpr (SCHEME == 0) {
+        lWf[0] = lw[0] * (1.0 + Df[2] * qinv);
+        lWf[3] = lw[3] - lw[0] * Df[2] * rK * qinv / pK;
+    } else {
+        lWf[0] = lw[0];
+        lWf[3] = lw[3];
+        // the frozen rho_K / (gamma p_K) at the target, and its own increments
+        gself[0] += lw[0] * Df[2] * qinv;
+        gself[3] -= lw[0] * Df[2] * rK * qinv / pK;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) O.addb(16 + t * 12 + FAM * 3 + q, wbP, 0, lDf[q]);
+    }
     // Q2 values at the foot -> nodes of the foot cell
     {
 #pragma unroll
@@ -278,16 +299,18 @@ __device__ void point_update_adj(const S_& S, const O_& O, int t, int i, int j, 
                 const int f = fam_of(a, b), off = (b == 2 ? RX : 0) + (a == 2 ? 1 : 0);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) O.addb(win_plane(f) + q, wb2, off, w * lWf[q]);
+                if constexpr (SCHEME == 0)
 #pragma unroll
-                for (int q = 0; q < 3; ++q) O.addb(16 + t * 12 + f * 3 + q, wb2, off, w * lDf[q]);
+                    for (int q = 0; q < 3; ++q) O.addb(16 + t * 12 + f * 3 + q, wb2, off, w * lDf[q]);
             }
     }
     // foot position: xi2 = 2 (off - floor(off)) - 1, off = ox - lam u1
     double lxi2 = 0.0, leta2 = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) { lxi2 += lWf[q] * dWx[q]; leta2 += lWf[q] * dWy[q]; }
+    if constexpr (SCHEME == 0)
 #pragma unroll
-    for (int q = 0; q < 3; ++q) { lxi2 += lDf[q] * dDx[q]; leta2 += lDf[q] * dDy[q]; }
+        for (int q = 0; q < 3; ++q) { lxi2 += lDf[q] * dDx[q]; leta2 += lDf[q] * dDy[q]; }
     const double lu1 = -2.0 * lam * lxi2, lv1 = -2.0 * lam * leta2;
     // first stage: u1 = Q2(u) at (xi1, eta1)
     {
@@ -427,7 +450,7 @@ __global__ void __launch_bounds__(kFNT, 2) k_adj_fwd(StatePtrs<double> prim, dou
 // Reverse sweep of one target (family FAM of node-cell (i, j)): the adjoints of the
 // edge fluxes it feeds, from the averages' cotangents, then of its three time levels
 // (w^n directly, w^{n+1/2} and w^{n+1} through the transposed point update).
-template <int FAM, class S_, class O_>
+template <int FAM, int SCHEME, class S_, class O_>
 __device__ void point_adj_target(const S_& S, const StatePtrs<double>& cot1, const O_& O, int nx, int ny, int i,
                                  int j, double gamma, double lam0, double lam1) {
     const int im = wrap1(i - 1, nx), jm = wrap1(j - 1, ny);
@@ -470,11 +493,11 @@ __device__ void point_adj_target(const S_& S, const StatePtrs<double>& cot1, con
         }
     }
     // n + 1/2 (weight 4/6) and n + 1 (weight 1/6; also an output of the step)
-    point_update_adj<FAM>(S, O, 0, i, j, w0, gamma, lam0, nuF, nuG, 4.0 / 6.0, nullptr, g);
+    point_update_adj<FAM, SCHEME>(S, O, 0, i, j, w0, gamma, lam0, nuF, nuG, 4.0 / 6.0, nullptr, g);
     const size_t c = (size_t)j * nx + i;
     const double extra[4] = {cot1.p[4 + 4 * FAM][c], cot1.p[5 + 4 * FAM][c], cot1.p[6 + 4 * FAM][c],
                              cot1.p[7 + 4 * FAM][c]};
-    point_update_adj<FAM>(S, O, 1, i, j, w0, gamma, lam1, nuF, nuG, 1.0 / 6.0, extra, g);
+    point_update_adj<FAM, SCHEME>(S, O, 1, i, j, w0, gamma, lam1, nuF, nuG, 1.0 / 6.0, extra, g);
 #pragma unroll
     for (int q = 0; q < 4; ++q) O.addb(win_plane(FAM) + q, wb, 0, g[q]);
 }
@@ -492,6 +515,7 @@ using PointStage = StageWin<kPRX, kPRY>;
 constexpr size_t kPointLds = sizeof(double) * 2 * 40 * kPWin;   // staged state + accumulators
 static_assert(kPWin <= kPNT, "one staging round");
 
+template <int SCHEME>
 __global__ void __launch_bounds__(kPNT) k_adj_points(StatePtrs<double> prim, const double* C, const double* Dfwd,
                                                      StatePtrs<double> cot1, PlaneList G, int nx, int ny,
                                                      double gamma, double lam0, double lam1) {
@@ -519,9 +543,9 @@ __global__ void __launch_bounds__(kPNT) k_adj_points(StatePtrs<double> prim, con
     const int cell = (int)threadIdx.x % (kPBX * kPBY), fam = (int)threadIdx.x / (kPBX * kPBY);   // wave-uniform
     const int i = i0 + cell % kPBX, j = j0 + cell / kPBX;
     if (i < nx && j < ny) {
-        if (fam == F_V) point_adj_target<F_V>(S, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
-        else if (fam == F_EV) point_adj_target<F_EV>(S, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
-        else point_adj_target<F_EH>(S, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
+        if (fam == F_V) point_adj_target<F_V, SCHEME>(S, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
+        else if (fam == F_EV) point_adj_target<F_EV, SCHEME>(S, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
+        else point_adj_target<F_EH, SCHEME>(S, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
     }
     __syncthreads();
     flush_window(O, G, nx, ny);
@@ -781,8 +805,12 @@ hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1_[16], vo
     {
         const size_t lds = kPointLds;   // allowed by prepare_adjoint_f64
         dim3 grd((a.nx + kPBX - 1) / kPBX, (a.ny + kPBY - 1) / kPBY);
-        hipLaunchKernelGGL(k_adj_points, grd, dim3(kPNT), lds, a.stream, prim, C, Dfwd, cot1, L, a.nx, a.ny,
-                           a.gamma, lam0, lam1);
+        if (a.scheme == 0)
+            hipLaunchKernelGGL(k_adj_points<0>, grd, dim3(kPNT), lds, a.stream, prim, C, Dfwd, cot1, L, a.nx, a.ny,
+                               a.gamma, lam0, lam1);
+        else
+            hipLaunchKernelGGL(k_adj_points<1>, grd, dim3(kPNT), lds, a.stream, prim, C, Dfwd, cot1, L, a.nx, a.ny,
+                               a.gamma, lam0, lam1);
     }
     {
         dim3 grd((a.nx + kIBX - 1) / kIBX, (a.ny + kIBY - 1) / kIBY);
@@ -799,7 +827,10 @@ hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1_[16], vo
 }
 
 hipError_t prepare_adjoint_f64() {
-    return hipFuncSetAttribute((const void*)k_adj_points, hipFuncAttributeMaxDynamicSharedMemorySize,
+    const hipError_t e = hipFuncSetAttribute((const void*)k_adj_points<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)kPointLds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_adj_points<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)kPointLds);
 }
 

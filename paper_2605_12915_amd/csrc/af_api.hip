@@ -154,6 +154,9 @@ af_status read_status(af_ctx* c, unsigned* bits) {
 // ---------------------------------------------------------------------------
 // Batching form
 // ---------------------------------------------------------------------------
+// Point-update scheme of a batch (all its grids share it; af_init_batch checks).
+static int batch_scheme(const af_ctx* c) { return (c->cfg.flags & AF_SCHEME_RB) ? 1 : 0; }
+
 // Work list of (instance, tile) for tile configuration `cfg`.
 hipError_t batch_build_work(af_ctx* c, int cfg) {
     const af::BatchTileCfg t = af::kBatchCfgs[cfg];
@@ -169,7 +172,7 @@ hipError_t batch_build_work(af_ctx* c, int cfg) {
     if (e == hipSuccess) e = hipMemcpy(c->d_work, w.data(), w.size() * sizeof(int2), hipMemcpyHostToDevice);
     c->nwork = (int)w.size();
     int per_cu = 1;
-    if (e == hipSuccess) e = af::batch_occupancy(cfg, &per_cu);
+    if (e == hipSuccess) e = af::batch_occupancy(cfg, batch_scheme(c), &per_cu);
     hipDeviceProp_t prop;
     if (e == hipSuccess) e = hipGetDeviceProperties(&prop, c->device);
     c->grid = t.direct ? c->nwork : (per_cu > 0 ? per_cu : 1) * prop.multiProcessorCount;
@@ -217,10 +220,12 @@ hipError_t batch_tune(af_ctx* c) {
         if (e == hipSuccess) e = batch_upload(c, c->stream);
         const int warm = 2, reps = 4;
         for (int r = 0; r < warm && e == hipSuccess; ++r)
-            e = af::launch_batch(cfg, c->d_binst, c->d_work, c->nwork, r & 1, c->status, c->grid, c->stream);
+            e = af::launch_batch(cfg, batch_scheme(c), c->d_binst, c->d_work, c->nwork, r & 1, c->status, c->grid,
+                                 c->stream);
         if (e == hipSuccess) e = hipEventRecord(c->ev[0], c->stream);
         for (int r = 0; r < reps && e == hipSuccess; ++r)
-            e = af::launch_batch(cfg, c->d_binst, c->d_work, c->nwork, r & 1, c->status, c->grid, c->stream);
+            e = af::launch_batch(cfg, batch_scheme(c), c->d_binst, c->d_work, c->nwork, r & 1, c->status, c->grid,
+                                 c->stream);
         if (e == hipSuccess) e = hipEventRecord(c->ev[1], c->stream);
         if (e == hipSuccess) e = hipEventSynchronize(c->ev[1]);
         float ms = 0.f;
@@ -257,7 +262,8 @@ hipError_t batch_graph(af_ctx* c, int nsteps, hipGraphExec_t* out) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
     for (int k = 0; k < nsteps && e == hipSuccess; ++k)
-        e = af::launch_batch(c->tune_cfg, c->d_binst, c->d_work, c->nwork, k & 1, c->status, c->grid, c->cap);
+        e = af::launch_batch(c->tune_cfg, batch_scheme(c), c->d_binst, c->d_work, c->nwork, k & 1, c->status, c->grid,
+                             c->cap);
     if (e == hipSuccess && (nsteps & 1)) e = af::launch_batch_copy(c->d_binst, c->nbatch, c->cap);
     hipError_t e2 = hipStreamEndCapture(c->cap, &g);
     if (e == hipSuccess) e = e2;
@@ -415,7 +421,7 @@ af_status af_read_status(af_ctx* c, af_status* status) {
 af_status af_step_adjoint(af_ctx* c, const af_state* primal_n, const af_state* cot_np1, af_state* cot_n,
                           double dt) {
     if (!c || !state_ok(primal_n) || !state_ok(cot_np1) || !state_ok(cot_n) || !(dt > 0.0)) return AF_ERR_ARG;
-    if (c->f32 || c->nbatch || (c->cfg.flags & AF_SCHEME_RB)) return AF_ERR_UNSUPPORTED;
+    if (c->f32 || c->nbatch) return AF_ERR_UNSUPPORTED;
     if (!c->adj_scratch) AF_HIP(hipMalloc(&c->adj_scratch, af::scratch_bytes_adjoint_f64(c->cfg.nx, c->cfg.ny)));
     af::StepArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -424,6 +430,7 @@ af_status af_step_adjoint(af_ctx* c, const af_state* primal_n, const af_state* c
     a.h = c->cfg.h;
     a.gamma = c->cfg.gamma;
     a.dt = dt;
+    a.scheme = (c->cfg.flags & AF_SCHEME_RB) ? 1 : 0;
     planes_of(primal_n, a.in);
     a.scratch = c->adj_scratch;
     a.status = c->status;
@@ -513,7 +520,7 @@ af_status af_init_batch(const af_config* cfgs, int32_t n, void* hip_stream, af_c
         if (cf.nx < 4 || cf.ny < 4 || !(cf.h > 0.0) || !(cf.gamma > 1.0) || !std::isfinite(cf.h)) return AF_ERR_ARG;
         if (cf.precision != AF_F32) return AF_ERR_UNSUPPORTED;
         if (!(cf.bg[0] > 0.0) || !(cf.bg[3] > 0.0)) return AF_ERR_ARG;
-        if (cf.flags & AF_SCHEME_RB) return AF_ERR_UNSUPPORTED;
+        if ((cf.flags & AF_SCHEME_RB) != (cfgs[0].flags & AF_SCHEME_RB)) return AF_ERR_UNSUPPORTED;   // one scheme per batch
     }
     af_ctx* c = new (std::nothrow) af_ctx();
     if (!c) return AF_ERR_ARG;
@@ -641,7 +648,8 @@ const char* af_dominant_kernel(af_ctx* c) {
         const af::BatchTileCfg t = af::kBatchCfgs[c->tune_cfg];
         c->kname = std::string(t.direct ? "af::k_fused_batch_direct<" : "af::k_fused_batch<") + std::to_string(t.tx) +
                    ", " + std::to_string(t.ty) + ", " + std::to_string(t.nt) +
-                   (t.direct ? ", " + std::to_string(t.minw) : std::string()) + ">";
+                   (t.direct ? ", " + std::to_string(t.minw) : std::string()) + ", " +
+                   std::to_string(batch_scheme(c)) + ">";
         return c->kname.c_str();
     }
     const bool rb = c && (c->cfg.flags & AF_SCHEME_RB);

@@ -36,9 +36,10 @@ struct BatchTileCfg { int tx, ty, nt; bool direct; int minw; };
 constexpr int kNumBatchCfgs = 14;
 extern const BatchTileCfg kBatchCfgs[kNumBatchCfgs];
 
-hipError_t batch_occupancy(int cfg, int* blocks_per_cu);
-hipError_t launch_batch(int cfg, const BatchInst* inst, const int2* work, int nwork, int parity, unsigned* status,
-                        int grid, hipStream_t s);
+// scheme: 0 transported (TAI), 1 additive (RB) point update, for the whole batch
+hipError_t batch_occupancy(int cfg, int scheme, int* blocks_per_cu);
+hipError_t launch_batch(int cfg, int scheme, const BatchInst* inst, const int2* work, int nwork, int parity,
+                        unsigned* status, int grid, hipStream_t s);
 hipError_t launch_batch_copy(const BatchInst* inst, int n, hipStream_t s);
 
 }  // namespace af

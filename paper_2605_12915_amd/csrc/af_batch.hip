@@ -18,20 +18,21 @@ namespace af {
 // the compiler keeps the tile body's constants live across iterations and spills;
 // as a call, the body gets the single-grid kernel's register allocation and the
 // loop pays only the callee-saved registers of one call per tile.
-template <int TX, int TY, int NT>
+template <int TX, int TY, int NT, int SCHEME>
 __device__ __noinline__ unsigned batch_tile(const BatchInst* __restrict__ inst, int2 it, int parity) {
     extern __shared__ __align__(16) unsigned char smem[];
     auto& L = *reinterpret_cast<FusedTile<float, TX, TY>*>(smem);
     const BatchInst& d = inst[it.x];
     const PlaneView in{{d.S[parity]}}, out{{d.S[parity ^ 1]}};
     unsigned st = 0;
-    fused_tile<float, PolPert<float>, TX, TY, NT, 0, true>(L, in, out, d.comp, d.nx, d.ny,
-                                                           (it.y % d.tiles_x) * TX, (it.y / d.tiles_x) * TY,
-                                                           d.pol, d.lam0, d.lam1, st);
+    fused_tile<float, PolPert<float>, TX, TY, NT, SCHEME, true>(L, in, out, d.comp, d.nx, d.ny,
+                                                                (it.y % d.tiles_x) * TX, (it.y / d.tiles_x) * TY,
+                                                                d.pol, d.lam0, d.lam1, st);
     return st;
 }
 
-template <int TX, int TY, int NT>
+// SCHEME (TAI 0, RB 1) is one for the whole batch.
+template <int TX, int TY, int NT, int SCHEME>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_fused_batch(const BatchInst* __restrict__ inst,
                                                     const int2* __restrict__ work, int nwork, int parity,
                                                     unsigned* status) {
@@ -48,7 +49,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
     const int w0 = b * chunk, w1 = min(nwork, w0 + chunk);
     unsigned st = 0;
     for (int w = w0; w < w1; ++w) {
-        st |= batch_tile<TX, TY, NT>(inst, work[w], parity);
+        st |= batch_tile<TX, TY, NT, SCHEME>(inst, work[w], parity);
         __syncthreads();          // the next tile reuses the LDS
     }
     if (st) atomicOr(status, st);
@@ -57,7 +58,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
 // Direct grid mode: one workgroup per work item (the hardware dispatcher balances the
 // load), tile body inlined exactly as in the single-grid kernel.  Work items are
 // numbered XCD-aware: each XCD gets a contiguous run of the list.
-template <int TX, int TY, int NT, int MINW>
+template <int TX, int TY, int NT, int MINW, int SCHEME>
 __global__ void __launch_bounds__(NT, MINW) k_fused_batch_direct(const BatchInst* __restrict__ inst,
                                                            const int2* __restrict__ work, int nwork, int parity,
                                                            unsigned* status) {
@@ -74,8 +75,8 @@ __global__ void __launch_bounds__(NT, MINW) k_fused_batch_direct(const BatchInst
     const BatchInst& d = inst[it.x];
     const PlaneView in{{d.S[parity]}}, out{{d.S[parity ^ 1]}};
     unsigned st = 0;
-    fused_tile<float, PolPert<float>, TX, TY, NT, 0, true>(L, in, out, d.comp, d.nx, d.ny, (it.y % d.tiles_x) * TX,
-                                                           (it.y / d.tiles_x) * TY, d.pol, d.lam0, d.lam1, st);
+    fused_tile<float, PolPert<float>, TX, TY, NT, SCHEME, true>(L, in, out, d.comp, d.nx, d.ny, (it.y % d.tiles_x) * TX,
+                                                                (it.y / d.tiles_x) * TY, d.pol, d.lam0, d.lam1, st);
     if (st) atomicOr(status, st);
 }
 
@@ -89,28 +90,42 @@ __global__ void __launch_bounds__(256) k_batch_copy(const BatchInst* inst, int n
     }
 }
 
-template <int TX, int TY, int NT, int MINW = 1>
-static hipError_t launch_cfg(bool direct, const BatchInst* inst, const int2* work, int nwork, int parity,
-                             unsigned* status, int grid, hipStream_t s) {
+template <int TX, int TY, int NT, int MINW, int SCHEME>
+static hipError_t launch_cfg_s(bool direct, const BatchInst* inst, const int2* work, int nwork, int parity,
+                               unsigned* status, int grid, hipStream_t s) {
     const size_t lds = sizeof(FusedTile<float, TX, TY>);
     if (direct)
-        hipLaunchKernelGGL((k_fused_batch_direct<TX, TY, NT, MINW>), dim3(nwork), dim3(NT), lds, s, inst, work, nwork,
-                           parity, status);
+        hipLaunchKernelGGL((k_fused_batch_direct<TX, TY, NT, MINW, SCHEME>), dim3(nwork), dim3(NT), lds, s, inst, work,
+                           nwork, parity, status);
     else
-        hipLaunchKernelGGL((k_fused_batch<TX, TY, NT>), dim3(grid), dim3(NT), lds, s, inst, work, nwork, parity, status);
+        hipLaunchKernelGGL((k_fused_batch<TX, TY, NT, SCHEME>), dim3(grid), dim3(NT), lds, s, inst, work, nwork, parity,
+                           status);
     return hipGetLastError();
 }
 
 template <int TX, int TY, int NT, int MINW = 1>
-static hipError_t occupancy_cfg(bool direct, int* blocks_per_cu) {
+static hipError_t launch_cfg(bool direct, int scheme, const BatchInst* inst, const int2* work, int nwork, int parity,
+                             unsigned* status, int grid, hipStream_t s) {
+    return scheme ? launch_cfg_s<TX, TY, NT, MINW, 1>(direct, inst, work, nwork, parity, status, grid, s)
+                  : launch_cfg_s<TX, TY, NT, MINW, 0>(direct, inst, work, nwork, parity, status, grid, s);
+}
+
+template <int TX, int TY, int NT, int MINW, int SCHEME>
+static hipError_t occupancy_cfg_s(bool direct, int* blocks_per_cu) {
     const size_t lds = sizeof(FusedTile<float, TX, TY>);
     if (direct)
-        return hipFuncSetAttribute((const void*)k_fused_batch_direct<TX, TY, NT, MINW>,
+        return hipFuncSetAttribute((const void*)k_fused_batch_direct<TX, TY, NT, MINW, SCHEME>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipError_t e = hipFuncSetAttribute((const void*)k_fused_batch<TX, TY, NT>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_fused_batch<TX, TY, NT, SCHEME>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused_batch<TX, TY, NT>, NT, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused_batch<TX, TY, NT, SCHEME>, NT, lds);
+}
+
+template <int TX, int TY, int NT, int MINW = 1>
+static hipError_t occupancy_cfg(bool direct, int scheme, int* blocks_per_cu) {
+    return scheme ? occupancy_cfg_s<TX, TY, NT, MINW, 1>(direct, blocks_per_cu)
+                  : occupancy_cfg_s<TX, TY, NT, MINW, 0>(direct, blocks_per_cu);
 }
 
 // Candidates: six tile shapes in the persistent mode, the same six direct, and 32x8 and
@@ -138,14 +153,14 @@ const BatchTileCfg kBatchCfgs[kNumBatchCfgs] = {
         }                                                         \
     }
 
-hipError_t batch_occupancy(int cfg, int* blocks_per_cu) {
+hipError_t batch_occupancy(int cfg, int scheme, int* blocks_per_cu) {
     *blocks_per_cu = 1;
-    AF_BATCH_SWITCH(occupancy_cfg, blocks_per_cu)
+    AF_BATCH_SWITCH(occupancy_cfg, scheme, blocks_per_cu)
 }
 
-hipError_t launch_batch(int cfg, const BatchInst* inst, const int2* work, int nwork, int parity, unsigned* status,
-                        int grid, hipStream_t s) {
-    AF_BATCH_SWITCH(launch_cfg, inst, work, nwork, parity, status, grid, s)
+hipError_t launch_batch(int cfg, int scheme, const BatchInst* inst, const int2* work, int nwork, int parity,
+                        unsigned* status, int grid, hipStream_t s) {
+    AF_BATCH_SWITCH(launch_cfg, scheme, inst, work, nwork, parity, status, grid, s)
 }
 
 #undef AF_BATCH_SWITCH

@@ -125,10 +125,10 @@ class Batch:
     gamma, background and dt) stepped together, one persistent launch per step, the
     nsteps launches replayed from a hipGraph (af_init_batch / af_step_batch)."""
 
-    def __init__(self, grids: Sequence[dict], check_errors: bool = False,
+    def __init__(self, grids: Sequence[dict], check_errors: bool = False, scheme: str = "tai",
                  stream: Optional[torch.cuda.Stream] = None, device: Optional[torch.device] = None):
         """grids: one dict per instance with keys nx, ny, h and optional gamma (1.4),
-        bg ((1, 0, 0, 1)), x0, y0."""
+        bg ((1, 0, 0, 1)), x0, y0.  scheme: "tai" or "rb", for every grid."""
         L = _lib.lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -143,7 +143,7 @@ class Batch:
             bg = g.get("bg", (1.0, 0.0, 0.0, 1.0))
             for k in range(4):
                 c.bg[k] = float(bg[k])
-            c.flags = AF_CHECK if check_errors else 0
+            c.flags = (AF_CHECK if check_errors else 0) | (AF_SCHEME_RB if scheme == "rb" else 0)
         self.cfgs = cfgs
         self.n = n
         self._ctx = ctypes.c_void_p()

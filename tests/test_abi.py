@@ -67,7 +67,7 @@ def test_bad_batch_config_rejected_on_host(L):
     cfgs[1].precision = _lib.AF_F64
     assert L.af_init_batch(cfgs, 2, None, ctypes.byref(ctx)) == _lib.AF_ERR_UNSUPPORTED
     cfgs[1].precision = _lib.AF_F32
-    cfgs[1].flags = _lib.AF_SCHEME_RB
+    cfgs[1].flags = _lib.AF_SCHEME_RB          # mixed point updates in one batch
     assert L.af_init_batch(cfgs, 2, None, ctypes.byref(ctx)) == _lib.AF_ERR_UNSUPPORTED
     cfgs[1].flags = 0
     cfgs[1].ny = 3

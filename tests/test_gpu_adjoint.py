@@ -24,48 +24,52 @@ def torch_dev():
     return torch, torch.device("cuda:0")
 
 
-def gpu_adjoint(torch_dev, P, s0, lam, dt):
+def gpu_adjoint(torch_dev, P, s0, lam, dt, scheme="tai"):
     torch, dev = torch_dev
     from paper_2605_12915_amd.stepper import Stepper
-    st = Stepper(P.nx, P.ny, P.h, P.gamma, device=dev)
+    st = Stepper(P.nx, P.ny, P.h, P.gamma, scheme=scheme, device=dev)
     g = st.adjoint(torch.from_numpy(s0).to(dev), torch.from_numpy(np.ascontiguousarray(lam)).to(dev), dt)
     torch.cuda.synchronize()
     return g.cpu().numpy()
 
 
-@pytest.mark.parametrize("nx,ny,seed", [(6, 5, 1), (7, 8, 2)])
-def test_adjoint_exact_vs_oracle_jacobian(torch_dev, orc, nx, ny, seed):
+@pytest.mark.parametrize("nx,ny,seed,scheme", [(6, 5, 1, "tai"), (7, 8, 2, "tai"), (6, 5, 3, "rb"), (7, 8, 4, "rb")])
+def test_adjoint_exact_vs_oracle_jacobian(torch_dev, orc, nx, ny, seed, scheme):
     P = I.random_smooth(nx, ny, seed=seed, amp=0.15, vel=(0.35, -0.25))
     s0 = P.state()
-    dt = P.dt_for_cfl(0.45)
+    # RB is stable only up to nu ~ 0.195 (Sec. 5.2); the Jacobian does not care, but
+    # keep both schemes at a step the paper runs them at
+    dt = P.dt_for_cfl(0.45 if scheme == "tai" else 0.19)
+    sch = 0 if scheme == "tai" else 1
     n = s0.size
     J = np.zeros((n, n))
     e = np.zeros(n)
     for k in range(n):
         e[:] = 0.0
         e[k] = 1.0
-        _, jv = orc.step_jvp(s0, e.reshape(s0.shape), P.h, P.gamma, dt, threads=1)
+        _, jv = orc.step_jvp(s0, e.reshape(s0.shape), P.h, P.gamma, dt, scheme=sch, threads=1)
         J[:, k] = jv.ravel()
     rng = np.random.default_rng(seed)
     lam = rng.normal(size=s0.shape)
     want = (J.T @ lam.ravel()).reshape(s0.shape)
-    got = gpu_adjoint(torch_dev, P, s0, lam, dt)
+    got = gpu_adjoint(torch_dev, P, s0, lam, dt, scheme)
     err = np.abs(got - want).max() / np.abs(want).max()
-    print("adjoint vs oracle J^T lambda: max rel", err)
+    print("adjoint vs oracle J^T lambda:", scheme, "max rel", err)
     assert err < 1e-11
 
 
-def test_adjoint_dot_product(torch_dev, orc):
+@pytest.mark.parametrize("scheme", ["tai", "rb"])
+def test_adjoint_dot_product(torch_dev, orc, scheme):
     P = I.isentropic_vortex(32, uinf=(1.0, 1.0))
     s0 = P.state()
-    dt = P.dt_for_cfl(0.4)
+    dt = P.dt_for_cfl(0.4 if scheme == "tai" else 0.19)
     rng = np.random.default_rng(7)
     for _ in range(3):
         v = rng.normal(size=s0.shape)
         lam = rng.normal(size=s0.shape)
-        _, jv = orc.step_jvp(s0, v, P.h, P.gamma, dt)
+        _, jv = orc.step_jvp(s0, v, P.h, P.gamma, dt, scheme=0 if scheme == "tai" else 1)
         lhs = float(np.sum(lam * jv))
-        rhs = float(np.sum(gpu_adjoint(torch_dev, P, s0, lam, dt) * v))
+        rhs = float(np.sum(gpu_adjoint(torch_dev, P, s0, lam, dt, scheme) * v))
         assert abs(lhs - rhs) <= 1e-11 * (abs(lhs) + np.sqrt(np.sum(lam ** 2) * np.sum(jv ** 2)) * 1e-3)
 
 

@@ -49,9 +49,9 @@ def pert_states(torch_dev, Ps):
     return [torch.from_numpy(to_perturbation(P.state(), P.bg, P.gamma)).to(dev) for P in Ps]
 
 
-def single(torch_dev, P, x, dt, n):
+def single(torch_dev, P, x, dt, n, scheme="tai"):
     from paper_2605_12915_amd.stepper import Stepper
-    st = Stepper(P.nx, P.ny, P.h, P.gamma, precision="f32", bg=P.bg, device=torch_dev[1])
+    st = Stepper(P.nx, P.ny, P.h, P.gamma, precision="f32", scheme=scheme, bg=P.bg, device=torch_dev[1])
     y = x.clone()
     st.step(y, dt, n)
     return y
@@ -75,6 +75,33 @@ def test_batch_tile_cfg_matches_single_grid(torch_dev, cfg, monkeypatch):
     for q, (g, w) in enumerate(zip(xs, want)):
         d = float((g - w).abs().max())
         assert d == 0.0, f"instance {q} ({Ps[q].nx}x{Ps[q].ny}): max diff {d}"
+
+
+@pytest.mark.parametrize("cfg", [0, 13])
+def test_batch_rb_scheme(torch_dev, orc, cfg, monkeypatch):
+    """Additive (RB) point update in both grid modes: bitwise equal to the single-grid
+    FP32 RB kernel, and within the FP32 bound of the oracle's RB step."""
+    torch, dev = torch_dev
+    from paper_2605_12915_amd.stepper import Batch, from_perturbation
+    monkeypatch.setenv("AF_BATCH_TILE", str(cfg))
+    Ps = problems()
+    dts = [P.dt_for_cfl(0.19) for P in Ps]    # RB is stable up to nu ~ 0.195 (Sec. 5.2)
+    xs = pert_states(torch_dev, Ps)
+    want = [single(torch_dev, P, x, dt, 6, "rb") for P, x, dt in zip(Ps, xs, dts)]
+    b = Batch(grids_of(Ps), check_errors=True, scheme="rb", device=dev)
+    b.step(xs, dts, 6)
+    torch.cuda.synchronize()
+    for q, (g, w) in enumerate(zip(xs, want)):
+        d = float((g - w).abs().max())
+        assert d == 0.0, f"instance {q} ({Ps[q].nx}x{Ps[q].ny}): max diff {d}"
+    for P, x, dt in zip(Ps, xs, dts):
+        s0 = P.state()
+        ref = orc.run(s0, P.h, P.gamma, dt, 6, scheme=1)
+        got = from_perturbation(x.cpu().numpy(), P.bg, P.gamma)
+        err = np.abs(got - ref).max(axis=(1, 2))
+        tol = f32_tolerance(ref, s0, P.bg, P.gamma, 6)
+        print(P.name, P.nx, P.ny, "RB batch vs oracle: max err/tol", (err / tol).max())
+        assert np.all(err <= tol), np.array2string(err / tol, precision=2)
 
 
 def test_batch_vs_oracle(torch_dev, orc):
