@@ -622,8 +622,14 @@ int orc_step_jvp(int nx, int ny, double h, double gamma, double dt, int scheme, 
     return st;
 }
 
-// Diagnostics of the state (Sec. 6 opening paragraph; Sec. 3 conservation):
-// out = {mass, momx, momy, energy, entropy, min_rho, min_p, max(|u|+c), max c dt/h}.
+// Diagnostics of the state (Sec. 6 opening paragraph; Sec. 3 conservation; the
+// vorticity integrals of the low-Mach shear experiment, Sec. 6):
+// out = {mass, momx, momy, energy, entropy, min_rho, min_p, max(|u|+c), max c dt/h,
+//        int omega dA, int omega^2 dA}.
+// omega = dv/dx - du/dy of the continuous piecewise-Q2 velocity reconstruction (the
+// nine nodal values of each cell, recovered centre included); per cell both integrals
+// use the 3x3 Gauss-Legendre rule, exact for omega (degree <= 2 in each direction) and
+// omega^2 (degree <= 4).
 int orc_diagnostics(int nx, int ny, double h, double gamma, double dt, const double* in, double* out) {
     Grid<double> G{nx, ny, h, gamma, in, {}};
     recover_centres(G, 1);
@@ -631,8 +637,15 @@ int orc_diagnostics(int nx, int ny, double h, double gamma, double dt, const dou
     double tot[4] = {0, 0, 0, 0};
     for (int k = 0; k < 4; ++k)
         for (int64_t c = 0; c < N; ++c) tot[k] += in[k * N + c];
-    double ent = 0.0, minr = 1e300, minp = 1e300, maxs = 0.0, maxr = 0.0;
+    double ent = 0.0, minr = 1e300, minp = 1e300, maxs = 0.0, maxr = 0.0, vort = 0.0, enst = 0.0;
     const double wq[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+    // Gauss-Legendre on [-1, 1]: nodes and weights
+    const double gs[3] = {-std::sqrt(0.6), 0.0, std::sqrt(0.6)}, gw[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+    // Lagrange basis on the nodes -1, 0, 1 and its derivative
+    auto lag = [](double t, double L[3], double dL[3]) {
+        L[0] = 0.5 * t * (t - 1.0); L[1] = 1.0 - t * t; L[2] = 0.5 * t * (t + 1.0);
+        dL[0] = t - 0.5;            dL[1] = -2.0 * t;   dL[2] = t + 0.5;
+    };
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             Prim<double> n[3][3];
@@ -644,6 +657,22 @@ int orc_diagnostics(int nx, int ny, double h, double gamma, double dt, const dou
                     e += wq[a] * wq[b] * w.r * std::log(w.p / std::pow(w.r, gamma));
                 }
             ent -= e;
+            // x = x_i + (1 + xi) h / 2: d/dx = (2 / h) d/dxi; the cell's area element h^2 / 4
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q) {
+                    double Lx[3], dLx[3], Ly[3], dLy[3];
+                    lag(gs[p], Lx, dLx);
+                    lag(gs[q], Ly, dLy);
+                    double dvdx = 0.0, dudy = 0.0;
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) {
+                            dvdx += dLx[a] * Ly[b] * n[a][b].v;
+                            dudy += Lx[a] * dLy[b] * n[a][b].u;
+                        }
+                    const double om = (2.0 / h) * (dvdx - dudy);
+                    vort += gw[p] * gw[q] * om;
+                    enst += gw[p] * gw[q] * om * om;
+                }
             for (int fam = 0; fam < 4; ++fam) {
                 Prim<double> w = G.node(fam, i, j);
                 double c = std::sqrt(gamma * w.p / w.r);
@@ -656,6 +685,7 @@ int orc_diagnostics(int nx, int ny, double h, double gamma, double dt, const dou
     double A = h * h;
     out[0] = tot[0] * A; out[1] = tot[1] * A; out[2] = tot[2] * A; out[3] = tot[3] * A;
     out[4] = ent * A; out[5] = minr; out[6] = minp; out[7] = maxs; out[8] = maxr;
+    out[9] = vort * A * 0.25; out[10] = enst * A * 0.25;
     return 0;
 }
 

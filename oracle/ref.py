@@ -131,7 +131,8 @@ def step_jvp(state, direction, h, gamma, dt, scheme=0, threads=None):
 def diagnostics(state, h, gamma, dt):
     s = _c(state)
     _, ny, nx = s.shape
-    out = np.zeros(9)
+    out = np.zeros(11)
     lib().orc_diagnostics(nx, ny, h, gamma, dt, _p(s), _p(out))
-    keys = ["mass", "momx", "momy", "energy", "entropy", "min_rho", "min_p", "max_speed", "max_acoustic_r"]
+    keys = ["mass", "momx", "momy", "energy", "entropy", "min_rho", "min_p", "max_speed", "max_acoustic_r",
+            "vorticity", "enstrophy"]
     return dict(zip(keys, out.tolist()))

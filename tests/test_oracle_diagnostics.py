@@ -105,3 +105,95 @@ def test_extremes_over_nodes(orc):
     # the centres matter: without them the extremes differ for this field
     nn = 3 * n * n
     assert rho[nn:].min() < rho[:nn].min() or spd[nn:].max() > spd[:nn].max()
+
+
+# Vorticity of the piecewise-Q2 velocity reconstruction.  For `field`:
+# omega = dv/dx - du/dy = -0.2 pi cos(2 pi x) + 0.4 pi sin(2 pi y), so over the unit
+# square int omega = 0 and int omega^2 = (0.2 pi)^2 / 2 + (0.4 pi)^2 / 2 = 0.1 pi^2.
+ENSTROPHY_EXACT = 0.1 * math.pi ** 2
+
+
+def test_vorticity_integral_vanishes_on_periodic_grids(orc):
+    # smooth data, and rough random node values: the reconstruction is continuous, so
+    # the cell integrals of its curl telescope to zero whatever the data
+    rng = np.random.default_rng(5)
+    for s in (problem(24).state(), problem(17).state() + 0.05 * rng.normal(size=(16, 17, 17)) * np.r_[
+            np.zeros(4), np.tile([0.0, 1.0, 1.0, 0.0], 3)][:, None, None]):
+        d = orc.diagnostics(s, 1.0 / s.shape[2], G, 1e-3)
+        assert abs(d["vorticity"]) < 1e-14 * max(1.0, math.sqrt(d["enstrophy"])), d["vorticity"]
+        assert d["enstrophy"] > 0.1
+
+
+def test_enstrophy_converges_to_exact(orc):
+    errs = []
+    for n in (8, 16, 32, 64):
+        P = problem(n)
+        errs.append(abs(orc.diagnostics(P.state(), P.h, G, 1e-3)["enstrophy"] - ENSTROPHY_EXACT))
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
+    print("enstrophy errors", errs, "orders", orders)
+    assert errs[-1] < 1e-5 * ENSTROPHY_EXACT
+    assert min(orders[1:]) > 3.5, orders
+
+
+def _transpose(s):
+    """Swap x and y: averages (rho, rho v, rho u, E), vertices (rho, v, u, p), and the
+    two edge families exchange (and swap their velocity components)."""
+    t = np.empty_like(s)
+    T = lambda a: a.T
+    t[0], t[1], t[2], t[3] = T(s[0]), T(s[2]), T(s[1]), T(s[3])
+    for dst, src in ((4, 4), (8, 12), (12, 8)):
+        t[dst], t[dst + 1], t[dst + 2], t[dst + 3] = T(s[src]), T(s[src + 2]), T(s[src + 1]), T(s[src + 3])
+    return t
+
+
+def test_vorticity_invariances(orc):
+    P = problem(20)
+    s = P.state()
+    d = orc.diagnostics(s, P.h, G, 1e-3)
+    # transposition maps omega to -omega
+    dt_ = orc.diagnostics(_transpose(s), P.h, G, 1e-3)
+    assert abs(dt_["enstrophy"] - d["enstrophy"]) <= 1e-13 * d["enstrophy"]
+    # scaling every velocity (point values, and the momentum averages from which the
+    # centre's velocity is recovered) scales the enstrophy by the square
+    s2 = s.copy()
+    s2[1] *= 3.0
+    s2[2] *= 3.0
+    for b in (4, 8, 12):
+        s2[b + 1] *= 3.0
+        s2[b + 2] *= 3.0
+    assert abs(orc.diagnostics(s2, P.h, G, 1e-3)["enstrophy"] - 9.0 * d["enstrophy"]) <= 1e-12 * d["enstrophy"]
+    # a uniform flow has none
+    s3 = s.copy()
+    for b in (4, 8, 12):
+        s3[b + 1] = 0.3
+        s3[b + 2] = -0.2
+    s3[1] = 0.3 * s3[0]
+    s3[2] = -0.2 * s3[0]
+    d3 = orc.diagnostics(s3, P.h, G, 1e-3)
+    assert abs(d3["enstrophy"]) < 1e-25 and abs(d3["vorticity"]) < 1e-15
+
+
+def _vel_problem(n, uf, vf):
+    def f(xv, yv):
+        X, Y = np.meshgrid(xv, yv)
+        return 1.0 + 0.0 * X, uf(X, Y), vf(X, Y), 1.0 + 0.0 * X
+    return I.Problem("vel_field", n, n, 0.0, 0.0, 1.0 / n, G, f)
+
+
+def test_enstrophy_sign_sensitive_and_irrotational(orc):
+    """u = 0.2 sin(2 pi (x + y)), v = 0.05 sin(2 pi (x + y)): omega = -0.3 pi cos(2 pi (x + y)),
+    int omega^2 = 0.045 pi^2 (a sign error between the two curl terms would give
+    (0.5 pi)^2 / 2 instead).  A gradient field u = phi_x, v = phi_y has omega = 0."""
+    w = lambda X, Y: np.sin(2 * math.pi * (X + Y))
+    exact = 0.045 * math.pi ** 2
+    e1, e2 = [], []
+    for n in (16, 32, 64):
+        P = _vel_problem(n, lambda X, Y: 0.2 * w(X, Y), lambda X, Y: 0.05 * w(X, Y))
+        e1.append(abs(orc.diagnostics(P.state(), P.h, G, 1e-3)["enstrophy"] - exact))
+        # phi = 0.1 sin(2 pi x) sin(2 pi y) / (2 pi)
+        Q = _vel_problem(n, lambda X, Y: 0.1 * np.cos(2 * math.pi * X) * np.sin(2 * math.pi * Y),
+                         lambda X, Y: 0.1 * np.sin(2 * math.pi * X) * np.cos(2 * math.pi * Y))
+        e2.append(orc.diagnostics(Q.state(), Q.h, G, 1e-3)["enstrophy"])
+    print("sign-sensitive errors", e1, "irrotational enstrophy", e2)
+    assert e1[-1] < 1e-5 * exact and math.log2(e1[-2] / e1[-1]) > 3.5
+    assert e2[-1] < 1e-6 and math.log2(e2[-2] / e2[-1]) > 3.5
