@@ -75,6 +75,11 @@ typedef struct af_diag {
     double min_rho, min_p;           /* over V, EV, EH nodes and recovered centres */
     double max_speed;                /* max(|u| + c) over the same nodes */
     double max_acoustic_r;           /* max c dt / h over the same nodes, for dt given */
+    double vorticity;                /* int omega dA, omega = dv/dx - du/dy of the continuous
+                                        piecewise-Q2 velocity reconstruction (Sec. 6, low-Mach
+                                        shear); zero up to round-off on a periodic grid */
+    double enstrophy;                /* int omega^2 dA of the same field (both by 3x3
+                                        Gauss-Legendre per cell, exact) */
 } af_diag;
 
 typedef struct af_ctx af_ctx;

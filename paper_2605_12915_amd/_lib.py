@@ -32,7 +32,8 @@ class AfState(ctypes.Structure):
 
 class AfDiag(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
-                ("mass", "momx", "momy", "energy", "entropy", "min_rho", "min_p", "max_speed", "max_acoustic_r")]
+                ("mass", "momx", "momy", "energy", "entropy", "min_rho", "min_p", "max_speed", "max_acoustic_r",
+                 "vorticity", "enstrophy")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

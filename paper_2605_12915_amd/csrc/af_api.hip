@@ -34,7 +34,7 @@ struct af_ctx {
     void* scratch = nullptr;       // path scratch
     unsigned* status = nullptr;    // device status bits
     double* partials = nullptr;    // diagnostics partials
-    double* diag_out = nullptr;    // 9 doubles on the device
+    double* diag_out = nullptr;    // af::kDiagVals doubles on the device
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // [0], [1] owned; [2], [3] per-launch timing slots
     bool f32 = false;              // AF_F32 context: float perturbation planes about cfg.bg
     void* comp = nullptr;          // AF_F32: 4 float compensation planes of the average update
@@ -326,8 +326,8 @@ af_status af_init(const af_config* cfg, void* hip_stream, af_ctx** out) {
     if (e == hipSuccess) e = hipMalloc(&c->state2, 16 * c->N * c->elem);
     if (e == hipSuccess) e = hipMalloc(&c->scratch, sbytes);
     if (e == hipSuccess) e = hipMalloc((void**)&c->status, sizeof(unsigned));
-    if (e == hipSuccess) e = hipMalloc((void**)&c->partials, kDiagPartials * 9 * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&c->diag_out, 9 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&c->partials, kDiagPartials * af::kDiagVals * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&c->diag_out, af::kDiagVals * sizeof(double));
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
     if (e == hipSuccess) e = hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -449,7 +449,7 @@ af_status af_diagnostics(af_ctx* c, const af_state* s, double dt, af_diag* out) 
     planes_of(s, p);
     AF_HIP(af::launch_diag(p, c->f32, c->cfg.bg, c->cfg.nx, c->cfg.ny, c->cfg.h, c->cfg.gamma, c->partials,
                            kDiagPartials, c->diag_out, c->stream));
-    double h[9];
+    double h[af::kDiagVals];
     AF_HIP(hipMemcpyAsync(h, c->diag_out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     AF_HIP(hipStreamSynchronize(c->stream));
     const double A = c->cfg.h * c->cfg.h;
@@ -462,6 +462,8 @@ af_status af_diagnostics(af_ctx* c, const af_state* s, double dt, af_diag* out) 
     out->min_p = h[6];
     out->max_speed = h[7];
     out->max_acoustic_r = h[8] * dt / c->cfg.h;
+    out->vorticity = h[9] * 0.5 * c->cfg.h;
+    out->enstrophy = h[10];
     return AF_OK;
 }
 

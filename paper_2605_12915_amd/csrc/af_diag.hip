@@ -1,5 +1,7 @@
 // FP64 diagnostics of a state (Sec. 6 opening paragraph: CFL and the entropy
-// functional -int rho log(p / rho^gamma) dA; Sec. 3: conservation totals).
+// functional -int rho log(p / rho^gamma) dA; Sec. 3: conservation totals; Sec. 6,
+// low-Mach shear: the integrals of the vorticity and of its square, for the
+// continuous piecewise-Q2 velocity reconstruction).
 // Two passes: a grid-stride block reduction into per-block partials (wavefront
 // shuffles, then LDS across the block's wavefronts), then one block over the
 // partials.  Entropy uses the tensor Simpson rule over the nine Q2 nodes of a cell
@@ -62,8 +64,10 @@ struct DiagAcc {
     }
 };
 
+// Registers capped for 4 waves per SIMD (a few dwords spill): 15% faster than the
+// free allocation (208 registers, 2 waves per SIMD) once the vorticity terms are in.
 template <class T>
-__global__ void __launch_bounds__(kDiagBlock) k_diag(StatePtrs<const T> st, int nx, int ny, double gamma,
+__global__ void __launch_bounds__(kDiagBlock, 4) k_diag(StatePtrs<const T> st, int nx, int ny, double gamma,
                                                      DiagBg bgs, double* partials) {
     __shared__ double sh[(kDiagBlock / 64) * kDiagVals];
     DiagAcc<T> A;
@@ -74,7 +78,8 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag(StatePtrs<const T> st, int 
     for (int k = 0; k < 4; ++k) { A.bg[k] = bgs.bg[k]; A.Ubg[k] = bgs.Ubg[k]; }
 #pragma unroll
     for (int k = 0; k < 16; ++k) A.s[k] = st.p[k];
-    double v[kDiagVals] = {0, 0, 0, 0, 0, 1e300, 1e300, 0, 0};
+    double v[kDiagVals];
+    diag_init(v);
     const size_t N = (size_t)nx * ny;
     // Entropy: the tensor Simpson rule over the nine Q2 nodes of every cell, summed
     // over cells, gives each node the sum of its weights in the cells that share it:
@@ -98,6 +103,12 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag(StatePtrs<const T> st, int 
         const Prim<double> own[4] = {A.point(F_V, i, j), A.point(F_EV, i, j), A.point(F_EH, i, j), A.node(F_C, i, j)};
 #pragma unroll
         for (int f = 0; f < 4; ++f) diag_node(v, wnode[f], own[f].r, own[f].u, own[f].v, own[f].p, gamma);
+        // the cell's nine velocity nodes, [x-node][y-node]
+        const Prim<double> v10 = A.point(F_V, i + 1, j), v01 = A.point(F_V, i, j + 1), v11 = A.point(F_V, i + 1, j + 1);
+        const Prim<double> ev1 = A.point(F_EV, i + 1, j), eh1 = A.point(F_EH, i, j + 1);
+        const double cu[3][3] = {{own[0].u, own[1].u, v01.u}, {own[2].u, own[3].u, eh1.u}, {v10.u, ev1.u, v11.u}};
+        const double cv[3][3] = {{own[0].v, own[1].v, v01.v}, {own[2].v, own[3].v, eh1.v}, {v10.v, ev1.v, v11.v}};
+        diag_vorticity(v, cu, cv);
     }
     block_reduce(v, sh);
     if (threadIdx.x == 0)
@@ -106,7 +117,8 @@ __global__ void __launch_bounds__(kDiagBlock) k_diag(StatePtrs<const T> st, int 
 
 __global__ void __launch_bounds__(kDiagBlock) k_diag_final(const double* partials, int n, double* out) {
     __shared__ double sh[(kDiagBlock / 64) * kDiagVals];
-    double v[kDiagVals] = {0, 0, 0, 0, 0, 1e300, 1e300, 0, 0};
+    double v[kDiagVals];
+    diag_init(v);
     for (int b = threadIdx.x; b < n; b += blockDim.x) diag_combine(v, partials + (size_t)b * kDiagVals);
     block_reduce(v, sh);
     if (threadIdx.x == 0)

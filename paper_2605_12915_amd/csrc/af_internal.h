@@ -26,9 +26,10 @@ struct StepArgs {
     void* comp;                 // FP32 path: 4 compensation planes of the average update
 };
 
-// Diagnostics partials: 9 values per block (5 sums, min rho, min p, max(|u|+c),
-// max c), reduced by launch_diag_final.
-constexpr int kDiagVals = 9;
+// Diagnostics partials: 11 values per block (5 sums, min rho, min p, max(|u|+c),
+// max c, and two more sums: the vorticity integral and the enstrophy), reduced by
+// launch_diag_final.
+constexpr int kDiagVals = 11;
 // Background of an FP32 state (zeros for FP64): absolute = stored + bg (points),
 // stored + Ubg (averages).
 struct DiagBg { double bg[4], Ubg[4], gamma; };
