@@ -1,0 +1,103 @@
+"""Drivers for the paper's numerical experiments on the GPU step (Sec. 4.2 mixed
+wave packet; Sec. 6 acoustic pulse, low-Mach shear, Kelvin-Helmholtz robustness).
+
+Every driver steps a seeded analytic initial condition (inputs.py) with the HIP
+step through the C ABI and reads the FP64 diagnostics (af_diagnostics) along the
+way; nothing here computes any part of the step.  The time step follows the
+paper's CFL definition, dt = CFL h / max(|u| + c), re-evaluated from the current
+state every `every` steps, the last step shortened to land on t_end.
+"""
+from __future__ import annotations
+
+import math
+import time
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import inputs as I
+from .stepper import Stepper
+
+
+def run(P: I.Problem, t_end: float, cfl: float, scheme: str = "tai", every: int = 10,
+        check_errors: bool = True, device: Optional[torch.device] = None) -> dict:
+    """Advance problem P to t_end.  Returns the final state (FP64 tensor on the
+    device), the number of steps, the wall time and the diagnostics history
+    [(t, diag dict)] sampled every `every` steps (first and last included)."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    st = Stepper(P.nx, P.ny, P.h, P.gamma, scheme=scheme, check_errors=check_errors, device=dev)
+    x = torch.from_numpy(P.state()).to(dev)
+    t, nsteps = 0.0, 0
+    d = st.diagnostics(x, 0.0)
+    hist = [(0.0, d)]
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    while t < t_end:
+        dt = cfl * P.h / d["max_speed"]
+        rest = t_end - t
+        last = rest <= every * dt
+        if last:                       # n equal steps, no larger than dt, that end on t_end
+            n = max(1, int(math.ceil(rest / dt - 1e-9)))
+            dt = rest / n
+        else:
+            n = every
+        st.step(x, dt, n)
+        t = t_end if last else t + n * dt
+        nsteps += n
+        d = st.diagnostics(x, dt)
+        hist.append((t, d))
+    torch.cuda.synchronize(dev)
+    return {"problem": P.name, "nx": P.nx, "ny": P.ny, "t": t, "steps": nsteps, "state": x,
+            "seconds": time.perf_counter() - t0, "history": hist, "stepper": st}
+
+
+def mixed_packet(n: int = 56, t_end: float = 1.0, cfl: float = 0.25, **kw) -> dict:
+    """Sec. 4.2: the linearised mixed packet (entropy, shear and two acoustic waves,
+    amplitudes 1e-6) against its exact solution; max point-value error / amplitude."""
+    P, at = I.mixed_packet(n)
+    r = run(P, t_end, cfl, **kw)
+    exact = I.make_state(at(r["t"]), n, n, 0.0, 0.0, P.h, P.gamma)
+    got = r["state"].cpu().numpy()
+    r["point_error_over_amplitude"] = float(np.abs(got[4:] - exact[4:]).max()) / 1e-6
+    r["average_error_over_amplitude"] = float(np.abs(got[:4] - exact[:4]).max()) / 1e-6
+    return r
+
+
+def pulse_asymmetry(n: int = 80, t_end: float = 2.5, cfl: float = 0.475, **kw) -> dict:
+    """Sec. 6, acoustic pulse on [-4, 4]^2: the exact solution is radially symmetric;
+    reports the vertex pressures' largest deviation under the transposition and the
+    two mirror symmetries of the grid, relative to the pulse amplitude."""
+    P = I.paper_pulse(n)
+    r = run(P, t_end, cfl, **kw)
+    p = r["state"][7].cpu().numpy()                     # vertex pressure, [j][i], vertex i at x = -4 + i h
+    flip = lambda a, ax: np.roll(np.flip(a, ax), 1, ax)  # x -> -x on vertices (index i -> -i mod n)
+    r["asymmetry"] = float(max(np.abs(p - p.T).max(), np.abs(p - flip(p, 0)).max(), np.abs(p - flip(p, 1)).max()))
+    r["amplitude"] = float(p.max() - p.min())
+    return r
+
+
+def low_mach_shear(nx: int = 64, t_end: float = 80.0, cfl: float = 0.45, **kw) -> dict:
+    """Sec. 6, low Mach number shear (M = 1e-2) on [0, 2] x [-0.5, 0.5]: time histories
+    of the vorticity integral (zero up to round-off), the enstrophy, the entropy
+    functional and the conserved totals."""
+    P = I.low_mach_shear(nx)
+    r = run(P, t_end, cfl, **kw)
+    H = r["history"]
+    r["max_abs_vorticity_integral"] = max(abs(d["vorticity"]) for _, d in H)
+    e0 = H[0][1]["enstrophy"]
+    r["enstrophy_ratio_final"] = H[-1][1]["enstrophy"] / e0
+    m0 = H[0][1]["mass"]
+    r["max_mass_drift"] = max(abs(d["mass"] - m0) for _, d in H) / abs(m0)
+    return r
+
+
+def kelvin_helmholtz(n: int = 64, t_end: float = 15.0, cfl: float = 0.475, **kw) -> dict:
+    """Sec. 6 robustness test on [-1, 1]^2 to t = 15 without limiters: completes when
+    no step raised a non-physical, foot or acoustic-CFL status (AF_CHECK)."""
+    P = I.kelvin_helmholtz(n)
+    r = run(P, t_end, cfl, **kw)
+    H = r["history"]
+    r["min_rho"] = min(d["min_rho"] for _, d in H)
+    r["min_p"] = min(d["min_p"] for _, d in H)
+    return r

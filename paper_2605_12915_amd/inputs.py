@@ -339,6 +339,40 @@ def mixed_packet(n: int, eps: float = 1e-6, M: float = 0.2, phi_deg: float = 25.
     return prob, at
 
 
+def low_mach_shear(nx: int = 64, ny: int | None = None, R: float = 1e-3, M: float = 1e-2, delta: float = 0.1,
+                   gamma: float = 1.4) -> Problem:
+    """Sec. 6, low Mach number shear: [0, 2] x [-0.5, 0.5], rho = gamma + R (1 - 2a(y)),
+    u = M (1 - 2a(y)), v = delta M sin(2 pi x), p = 1, with the smoothed indicator a(y)
+    of the band |y| < 1/4 (sine ramps of width 1/16)."""
+    ny = nx // 2 if ny is None else ny
+
+    def a_of(y):
+        a = np.zeros_like(y)
+        a = np.where((y >= -9 / 32) & (y < -7 / 32), 0.5 * (1.0 + np.sin(16 * math.pi * (y + 0.25))), a)
+        a = np.where((y >= -7 / 32) & (y < 7 / 32), 1.0, a)
+        a = np.where((y >= 7 / 32) & (y < 9 / 32), 0.5 * (1.0 - np.sin(16 * math.pi * (y - 0.25))), a)
+        return a
+
+    def prim(xv, yv):
+        X, Y = np.meshgrid(xv, yv)
+        a = a_of(Y)
+        return gamma + R * (1.0 - 2.0 * a), M * (1.0 - 2.0 * a), delta * M * np.sin(2 * math.pi * X), np.ones_like(X)
+
+    assert 2 * ny == nx, "the domain is 2 x 1 with square cells"
+    return Problem("low_mach_shear", nx, ny, 0.0, -0.5, 2.0 / nx, gamma, prim, bg=(gamma, 0.0, 0.0, 1.0))
+
+
+def kelvin_helmholtz(n: int = 64, gamma: float = 1.4) -> Problem:
+    """Sec. 6, robustness test: [-1, 1]^2, B(y) = tanh(15y + 7.5) - tanh(15y - 7.5),
+    rho = 1/2 + 3/4 B, u = (B - 1)/2, v = sin(2 pi x)/10, p = 1."""
+    def prim(xv, yv):
+        X, Y = np.meshgrid(xv, yv)
+        B = np.tanh(15 * Y + 7.5) - np.tanh(15 * Y - 7.5)
+        return 0.5 + 0.75 * B, 0.5 * (B - 1.0), 0.1 * np.sin(2 * math.pi * X), np.ones_like(X)
+
+    return Problem("kelvin_helmholtz", n, n, -1.0, -1.0, 2.0 / n, gamma, prim, bg=(1.0, 0.0, 0.0, 1.0))
+
+
 def batch_sizes(count: int = 64, lo: int = 32, hi: int = 1024, seed: int = 5):
     """Log-uniform instance sizes N_k = round(exp U[ln lo, ln hi])."""
     rng = np.random.Generator(np.random.PCG64(seed))

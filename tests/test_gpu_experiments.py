@@ -1,0 +1,100 @@
+"""The paper's experiments run on the GPU step (paper_2605_12915_amd/experiments.py):
+the behaviour the paper reports, and the same runs against the oracle over a short
+horizon at fixed dt."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2605_12915_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+def gpu_fixed(torch_dev, P, dt, n, scheme="tai"):
+    torch, dev = torch_dev
+    from paper_2605_12915_amd.stepper import Stepper
+    st = Stepper(P.nx, P.ny, P.h, P.gamma, scheme=scheme, check_errors=True, device=dev)
+    x = torch.from_numpy(P.state()).to(dev)
+    st.step(x, dt, n)
+    torch.cuda.synchronize()
+    return x.cpu().numpy()
+
+
+def normwise(got, want):
+    return max(float(np.linalg.norm(got[k] - want[k]) / max(np.linalg.norm(want[k]), 1e-300))
+               for k in range(16))
+
+
+def test_mixed_packet_exact_solution(torch_dev, orc):
+    """Sec. 4.2 packet, 56^2, nu = 0.25, to t = 1: the point values within 3% of the
+    amplitude of the exact solution; at fixed dt the GPU equals the oracle."""
+    from paper_2605_12915_amd import experiments as E
+    r = E.mixed_packet(56, 1.0, 0.25, device=torch_dev[1])
+    print("mixed packet:", r["steps"], "steps, point error / amplitude", r["point_error_over_amplitude"])
+    assert r["t"] == 1.0
+    assert r["point_error_over_amplitude"] < 0.03
+    P, at = I.mixed_packet(56)
+    n = 300
+    dt = 1.0 / n
+    got = gpu_fixed(torch_dev, P, dt, n)
+    want = orc.run(P.state(), P.h, P.gamma, dt, n)
+    # the waves are 1e-6 of the background: compare the perturbations
+    err = float(np.abs(got - want).max()) / 1e-6
+    print("mixed packet GPU vs oracle (300 steps): max diff / amplitude", err)
+    assert err < 1e-8
+
+
+def test_pulse_radial_symmetry(torch_dev, orc):
+    """Sec. 6 pulse on [-4, 4]^2, 80^2, CFL 0.475, t = 2.5: symmetric under the grid's
+    transposition and mirrors to round-off; GPU equals the oracle at fixed dt."""
+    from paper_2605_12915_amd import experiments as E
+    r = E.pulse_asymmetry(80, 2.5, 0.475, device=torch_dev[1])
+    print("pulse:", r["steps"], "steps, asymmetry", r["asymmetry"], "amplitude", r["amplitude"])
+    assert r["asymmetry"] <= 1e-12 * r["amplitude"]
+    P = I.paper_pulse(80)
+    dt = P.dt_for_cfl(0.475)
+    got = gpu_fixed(torch_dev, P, dt, 55)
+    want = orc.run(P.state(), P.h, P.gamma, dt, 55)
+    assert normwise(got, want) <= 1e-12
+
+
+def test_low_mach_shear_vorticity_integrals(torch_dev, orc):
+    """Sec. 6 low-Mach shear, 64 x 32 to t = 80 (~5800 steps): the vorticity integral
+    stays at round-off, mass is conserved, the enstrophy declines but is not wiped out;
+    the first 200 steps equal the oracle's."""
+    from paper_2605_12915_amd import experiments as E
+    r = E.low_mach_shear(64, 80.0, 0.45, device=torch_dev[1])
+    H = r["history"]
+    print("low-Mach shear:", r["steps"], "steps,", "max |int omega|", r["max_abs_vorticity_integral"],
+          "enstrophy ratio", r["enstrophy_ratio_final"], "mass drift", r["max_mass_drift"],
+          "entropy", H[0][1]["entropy"], "->", H[-1][1]["entropy"])
+    assert r["t"] == 80.0
+    assert r["max_abs_vorticity_integral"] < 1e-15
+    assert r["max_mass_drift"] < 1e-14
+    assert 0.2 < r["enstrophy_ratio_final"] < 1.0
+    P = I.low_mach_shear(64)
+    dt = P.dt_for_cfl(0.45)
+    got = gpu_fixed(torch_dev, P, dt, 200)
+    want = orc.run(P.state(), P.h, P.gamma, dt, 200)
+    # perturbations are 1e-2 (velocity) to 1e-3 (density) of the background
+    assert float(np.abs(got - want).max()) < 1e-12
+
+
+@pytest.mark.parametrize("scheme,cfl", [("tai", 0.475), ("rb", 0.25)])
+def test_kelvin_helmholtz_robustness(torch_dev, scheme, cfl):
+    """Sec. 6 robustness test, 64^2 to t = 15 at the paper's CFL numbers, no limiter:
+    every step passes the non-physical, foot and acoustic-CFL checks."""
+    from paper_2605_12915_amd import experiments as E
+    r = E.kelvin_helmholtz(64, 15.0, cfl, scheme=scheme, device=torch_dev[1])
+    print("Kelvin-Helmholtz", scheme, r["steps"], "steps, min rho", r["min_rho"], "min p", r["min_p"])
+    assert r["t"] == 15.0
+    assert r["min_rho"] > 0.0 and r["min_p"] > 0.0

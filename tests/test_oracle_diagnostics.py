@@ -197,3 +197,24 @@ def test_enstrophy_sign_sensitive_and_irrotational(orc):
     print("sign-sensitive errors", e1, "irrotational enstrophy", e2)
     assert e1[-1] < 1e-5 * exact and math.log2(e1[-2] / e1[-1]) > 3.5
     assert e2[-1] < 1e-6 and math.log2(e2[-2] / e2[-1]) > 3.5
+
+
+def test_experiment_initial_data():
+    """Sec. 6 initial data as stated: the shear's band indicator a(y) is 1 inside
+    |y| < 7/32, 0 outside |y| >= 9/32 and continuous (with its slope) at the four
+    breakpoints; the Kelvin-Helmholtz layer has rho in [1/2, 2] and u = (B - 1)/2."""
+    P = I.low_mach_shear(64)
+    assert (P.nx, P.ny, P.x0, P.y0, P.h) == (64, 32, 0.0, -0.5, 2.0 / 64)
+    y = np.array([-0.5, -9 / 32 - 1e-12, -9 / 32, -7 / 32 - 1e-12, -7 / 32, 0.0, 7 / 32 - 1e-12, 7 / 32,
+                  9 / 32 - 1e-12, 9 / 32, 0.49])
+    rho, u, v, p = P.prim(np.array([0.25]), y)
+    a = (1.0 - u[:, 0] / 1e-2) / 2.0
+    assert np.allclose(a, [0, 0, 0, 1, 1, 1, 1, 1, 0, 0, 0], atol=1e-9)
+    assert np.allclose(rho[:, 0], G + 1e-3 * (1.0 - 2.0 * a)) and np.allclose(p, 1.0)
+    assert np.allclose(v, 0.1 * 1e-2 * math.sin(2 * math.pi * 0.25))
+    Q = I.kelvin_helmholtz(64)
+    rho, u, v, p = Q.prim(np.array([-1.0, -0.25, 0.5]), np.array([-1.0, 0.0, 0.9]))
+    B = np.tanh(15 * np.array([-1.0, 0.0, 0.9]) + 7.5) - np.tanh(15 * np.array([-1.0, 0.0, 0.9]) - 7.5)
+    assert np.allclose(rho, (0.5 + 0.75 * B)[:, None]) and np.allclose(u, (0.5 * (B - 1.0))[:, None])
+    assert np.allclose(v, 0.1 * np.sin(2 * math.pi * np.array([-1.0, -0.25, 0.5]))[None, :]) and np.allclose(p, 1.0)
+    assert 0.5 - 1e-6 < rho.min() and rho.max() < 2.0
