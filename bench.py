@@ -54,20 +54,24 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-n", type=int, default=512)
-    ap.add_argument("--cpu-sample-steps", type=int, default=6)
+    ap.add_argument("--cpu-sample-n", type=int, default=0,
+                    help="grid of the oracle sample (0: the headline grid and state itself)")
+    ap.add_argument("--cpu-sample-steps", type=int, default=8)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
-def cpu_baseline(n: int, steps: int):
-    """The oracle as it stands, on the host cores, over a bounded sample of the same
-    workload family (smaller grid, few steps)."""
+def cpu_baseline(n: int, steps: int, P=None, s=None):
+    """The oracle as it stands, on the host cores, over a bounded sample of the
+    workload: the headline grid and state (P, s) for a few steps, or an n x n grid of
+    the same flow."""
     from oracle import ref
     from paper_2605_12915_amd import inputs as I
-    P = I.fourier_modes(n)
-    s = P.state()
+    if P is None:
+        P = I.fourier_modes(n)
+        s = P.state()
+    n = P.nx
     dt = P.dt_for_cfl(0.4)
     threads = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
@@ -370,7 +374,10 @@ def main():
         line["forms"]["batch"] = form_batch(torch, dev, args.batch_count, args.batch_steps, big32)
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        line["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, args.cpu_sample_steps)
+        if args.cpu_sample_n:
+            line["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, args.cpu_sample_steps)
+        else:
+            line["cpu_baseline"] = cpu_baseline(P.nx, args.cpu_sample_steps, P, s0)
     print(json.dumps(line))
 
 
