@@ -98,11 +98,36 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
     const bool onex = nx >= Tile::PX, oney = ny >= Tile::PY;
 
     // ---- phase 0: primitive node values of cells [-2, T+3)^2 ------------------------
-    for (int e = tid; e < Tile::PX * Tile::PY; e += NT) {
-        const int x = e % Tile::PX, y = e / Tile::PX;
-        const size_t g = (size_t)wrap_win(j0 + y - 2, ny, oney) * nx + wrap_win(i0 + x - 2, nx, onex);
+    if constexpr (sizeof(T) == 8) {
+        // every round's loads issued before the first store: the window has slightly more
+        // node-cells than threads, and a second load round trip would hold the whole
+        // workgroup at the barrier (1.5% faster; in FP32 the extra live registers cost more)
+        constexpr int NP0 = Tile::PX * Tile::PY, R0 = (NP0 + NT - 1) / NT;
+        T pv[R0][12];
 #pragma unroll
-        for (int k = 0; k < 12; ++k) L.P[k][y][x] = in.p[4 + k][g];
+        for (int r = 0; r < R0; ++r) {
+            const int e = r * NT + tid;
+            if (e < NP0) {
+                const int x = e % Tile::PX, y = e / Tile::PX;
+                const size_t g = (size_t)wrap_win(j0 + y - 2, ny, oney) * nx + wrap_win(i0 + x - 2, nx, onex);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) pv[r][k] = in.p[4 + k][g];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int e = r * NT + tid;
+            if (e < NP0)
+#pragma unroll
+                for (int k = 0; k < 12; ++k) L.P[k][e / Tile::PX][e % Tile::PX] = pv[r][k];
+        }
+    } else {
+        for (int e = tid; e < Tile::PX * Tile::PY; e += NT) {
+            const int x = e % Tile::PX, y = e / Tile::PX;
+            const size_t g = (size_t)wrap_win(j0 + y - 2, ny, oney) * nx + wrap_win(i0 + x - 2, nx, onex);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) L.P[k][y][x] = in.p[4 + k][g];
+        }
     }
     __syncthreads();
 
