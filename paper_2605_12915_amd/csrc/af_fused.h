@@ -233,6 +233,30 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
             }
         }
     }
+    // FP32: the owned cells' time-n averages and compensation for phase 4 are loaded
+    // here, so that their latency overlaps the flux stores and the two barriers (5%
+    // faster; in FP64 the registers they hold across the barriers cost 0.7%).
+    constexpr bool kEarlyAvg = sizeof(T) == 4;
+    constexpr int R4 = (TX * TY + NT - 1) / NT;
+    T oldv[R4][4], oldc[R4][4];
+    if constexpr (kEarlyAvg) {
+#pragma unroll
+        for (int r = 0; r < R4; ++r) {
+            const int e = r * NT + tid;
+            const int x = e % TX, y = e / TX;
+            if (e < TX * TY && i0 + x < nx && j0 + y < ny) {
+                const size_t g = (size_t)(j0 + y) * nx + (i0 + x);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) oldv[r][k] = in.p[k][g];
+                if constexpr (KAHAN) {
+                    const size_t N = (size_t)nx * ny;
+                    auto* __restrict__ cg = (__attribute__((address_space(1))) T*)comp;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) oldc[r][k] = cg[k * N + g];
+                }
+            }
+        }
+    }
     __syncthreads();     // every read of D is done: the flux arrays may alias it
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
@@ -255,29 +279,59 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
     __syncthreads();
 
     // ---- phase 4: average update of the owned cells -----------------------------------
-    for (int e = tid; e < TX * TY; e += NT) {
-        const int x = e % TX, y = e / TX;
-        if (i0 + x >= nx || j0 + y >= ny) continue;
-        const size_t g = (size_t)(j0 + y) * nx + (i0 + x);
+    // -lam1 times the divergence of the cell's four space-time Simpson edge fluxes
+    auto delta_of = [&](int x, int y, int k) -> T {
+        const T Fl = (L.F.FV[k][y][x] + T(4) * L.F.FE[k][y][x] + L.F.FV[k][y + 1][x]) * T(1.0 / 6.0);
+        const T Fr = (L.F.FV[k][y][x + 1] + T(4) * L.F.FE[k][y][x + 1] + L.F.FV[k][y + 1][x + 1]) * T(1.0 / 6.0);
+        const T Gb = (L.F.FV[4 + k][y][x] + T(4) * L.F.GE[k][y][x] + L.F.FV[4 + k][y][x + 1]) * T(1.0 / 6.0);
+        const T Gt = (L.F.FV[4 + k][y + 1][x] + T(4) * L.F.GE[k][y + 1][x] + L.F.FV[4 + k][y + 1][x + 1]) * T(1.0 / 6.0);
+        return -lam1 * ((Fr - Fl) + (Gt - Gb));
+    };
+    if constexpr (kEarlyAvg) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const T Fl = (L.F.FV[k][y][x] + T(4) * L.F.FE[k][y][x] + L.F.FV[k][y + 1][x]) * T(1.0 / 6.0);
-            const T Fr = (L.F.FV[k][y][x + 1] + T(4) * L.F.FE[k][y][x + 1] + L.F.FV[k][y + 1][x + 1]) * T(1.0 / 6.0);
-            const T Gb = (L.F.FV[4 + k][y][x] + T(4) * L.F.GE[k][y][x] + L.F.FV[4 + k][y][x + 1]) * T(1.0 / 6.0);
-            const T Gt = (L.F.FV[4 + k][y + 1][x] + T(4) * L.F.GE[k][y + 1][x] + L.F.FV[4 + k][y + 1][x + 1]) * T(1.0 / 6.0);
-            const T delta = -lam1 * ((Fr - Fl) + (Gt - Gb));
-            if constexpr (KAHAN) {
-                // compensated sum: the low-order part lost when adding delta is carried
-                // in comp and fed back into the next step's increment
-                const size_t N = (size_t)nx * ny;
-                auto* __restrict__ cg = (__attribute__((address_space(1))) T*)comp;
-                const T old = in.p[k][g];
-                const T y_ = delta - cg[k * N + g];
-                const T t_ = old + y_;
-                cg[k * N + g] = (t_ - old) - y_;
-                out.p[k][g] = t_;
-            } else {
-                out.p[k][g] = in.p[k][g] + delta;
+        for (int r = 0; r < R4; ++r) {
+            const int e = r * NT + tid;
+            if (e >= TX * TY) continue;
+            const int x = e % TX, y = e / TX;
+            if (i0 + x >= nx || j0 + y >= ny) continue;
+            const size_t g = (size_t)(j0 + y) * nx + (i0 + x);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const T delta = delta_of(x, y, k);
+                if constexpr (KAHAN) {
+                    // compensated sum: the low-order part lost when adding delta is carried
+                    // in comp and fed back into the next step's increment
+                    const size_t N = (size_t)nx * ny;
+                    auto* __restrict__ cg = (__attribute__((address_space(1))) T*)comp;
+                    const T old = oldv[r][k];
+                    const T y_ = delta - oldc[r][k];
+                    const T t_ = old + y_;
+                    cg[k * N + g] = (t_ - old) - y_;
+                    out.p[k][g] = t_;
+                } else {
+                    out.p[k][g] = oldv[r][k] + delta;
+                }
+            }
+        }
+    } else {
+        for (int e = tid; e < TX * TY; e += NT) {
+            const int x = e % TX, y = e / TX;
+            if (i0 + x >= nx || j0 + y >= ny) continue;
+            const size_t g = (size_t)(j0 + y) * nx + (i0 + x);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const T delta = delta_of(x, y, k);
+                if constexpr (KAHAN) {
+                    const size_t N = (size_t)nx * ny;
+                    auto* __restrict__ cg = (__attribute__((address_space(1))) T*)comp;
+                    const T old = in.p[k][g];
+                    const T y_ = delta - cg[k * N + g];
+                    const T t_ = old + y_;
+                    cg[k * N + g] = (t_ - old) - y_;
+                    out.p[k][g] = t_;
+                } else {
+                    out.p[k][g] = in.p[k][g] + delta;
+                }
             }
         }
     }
