@@ -106,17 +106,21 @@ struct StageWin {
     }
 };
 
-// Add an LDS window to its global planes (periodic wrap), one atomic per nonzero entry.
+// Add an LDS window to its global planes (periodic wrap), one atomic per nonzero entry:
+// each thread takes whole node-cells of the window, wraps its global index once and
+// walks the planes (so the plane pointer is the same across the wavefront).
 template <int NPL, int RX, int RY>
 __device__ __forceinline__ void flush_window(const LdsWin<NPL, RX, RY>& w, const PlaneList& G, int nx, int ny) {
-    for (int e = threadIdx.x; e < NPL * RX * RY; e += blockDim.x) {
-        const double v = w.a[e];
-        if (v == 0.0) continue;
-        const int pl = e / (RX * RY), r = e - pl * (RX * RY);
-        int i = w.ri0 + r % RX, j = w.rj0 + r / RX;
+    for (int e = threadIdx.x; e < RX * RY; e += blockDim.x) {
+        int i = w.ri0 + e % RX, j = w.rj0 + e / RX;
         i = (i % nx + nx) % nx;
         j = (j % ny + ny) % ny;
-        atomicAdd(G.p[pl] + (size_t)j * nx + i, v);
+        const size_t k = (size_t)j * nx + i;
+#pragma unroll 8
+        for (int pl = 0; pl < NPL; ++pl) {
+            const double v = w.a[pl * (RX * RY) + e];
+            if (v != 0.0) atomicAdd(G.p[pl] + k, v);
+        }
     }
 }
 
