@@ -73,15 +73,9 @@ struct LdsWin {
     }
     // add g = (d rho, d u, d v, d p) to node fam of cell (i, j)
     __device__ __forceinline__ void node(int fam, int i, int j, const double g[4]) const {
-        const int b = fam == F_C ? 12 : 4 * fam;
+        const int b = fam == F_C ? 12 : 4 * fam, o = base(i, j);
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (g[q] != 0.0) add(b + q, i, j, g[q]);
-    }
-    __device__ __forceinline__ void inc(int t, int fam, int i, int j, const double g[3]) const {
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-            if (g[q] != 0.0) add(16 + t * 12 + fam * 3 + q, i, j, g[q]);
+        for (int q = 0; q < 4; ++q) addb(b + q, o, 0, g[q]);
     }
     __device__ __forceinline__ void zero() const {
         for (int e = threadIdx.x; e < NPL * RX * RY; e += blockDim.x) a[e] = 0.0;
@@ -122,14 +116,6 @@ __device__ __forceinline__ void flush_window(const LdsWin<NPL, RX, RY>& w, const
             if (v != 0.0) atomicAdd(G.p[pl] + k, v);
         }
     }
-}
-
-// Node (family, cell offset) of entry [a][b] of cell (ci, cj) (Sec. 2 layout).
-__device__ __forceinline__ void node_of(int a, int b, int ci, int cj, int& fam, int& i, int& j) {
-    const int fa[3][3] = {{F_V, F_EV, F_V}, {F_EH, F_C, F_EH}, {F_V, F_EV, F_V}};   // [a][b]
-    fam = fa[a][b];
-    i = ci + (a == 2 ? 1 : 0);
-    j = cj + (b == 2 ? 1 : 0);
 }
 
 // Family of node [a][b] of a cell, the node-cell (dx, dy) of the cell's 2x2 block of
@@ -567,6 +553,7 @@ __device__ __forceinline__ void mono1_T(double c0, double c1, double c2, double&
 // scattered to the nodes of cell (ci, cj).
 template <int W, int XC, int YC, class O_>
 __device__ __forceinline__ void wedge_adj(const double la[6][4], const O_& O, int ci, int cj) {
+    constexpr int RX = O_::kRX;
     double lc[3][3][3];
 #pragma unroll
     for (int v = 0; v < 3; ++v)
@@ -604,14 +591,15 @@ __device__ __forceinline__ void wedge_adj(const double la[6][4], const O_& O, in
 #pragma unroll
         for (int b = 0; b < 3; ++b) mono1_T<XC>(lg[0][b], lg[1][b], lg[2][b], lf[v][0][b], lf[v][1][b], lf[v][2][b]);
     }
+    const int wb = O.base(ci, cj);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            int fam, ii, jj;
-            node_of(a, b, ci, cj, fam, ii, jj);
-            const double g[4] = {0.0, lf[1][a][b], lf[2][a][b], lf[0][a][b]};
-            O.node(fam, ii, jj, g);
+            const int pl = win_plane(fam_of(a, b)), off = (b == 2 ? RX : 0) + (a == 2 ? 1 : 0);
+            O.addb(pl + 1, wb, off, lf[1][a][b]);
+            O.addb(pl + 2, wb, off, lf[2][a][b]);
+            O.addb(pl + 3, wb, off, lf[0][a][b]);
         }
 }
 
@@ -675,9 +663,11 @@ __device__ void incr_adj(const AdjNodes& A, const O_& O, const double* lD, int i
     }
     lZ += -iZ * iZ * liZ;
     // c = sqrt(gamma p / rho), Z = rho c
-    const double gK[4] = {lc * (-c / (2.0 * W.r)) + lZ * (0.5 * c), 0.0, 0.0,
-                          lc * (c / (2.0 * W.p)) + lZ * (W.r * c / (2.0 * W.p))};
-    O.node(FAM, i, j, gK);
+    {
+        const int wb = O.base(i, j);
+        O.addb(win_plane(FAM), wb, 0, lc * (-c / (2.0 * W.r)) + lZ * (0.5 * c));
+        O.addb(win_plane(FAM) + 3, wb, 0, lc * (c / (2.0 * W.p)) + lZ * (W.r * c / (2.0 * W.p)));
+    }
     if constexpr (FAM == F_V) {
         wedge_adj<W_V_NE, 0, 0>(la, O, i, j);
         wedge_adj<W_V_NW, 1, 0>(la, O, i - 1, j);
