@@ -1,24 +1,25 @@
 // Reverse-mode derivative of one FP64 RB-TAI step (transposed Sec. 6.1 dataflow).
 //
-// cot_n = (d step / d state_n)^T cot_np1 at fixed dt.  The forward intermediates
-// (recovered centres W^C and the node increments of both durations) are recomputed
-// from state_n by the multi-kernel path's k_centre/k_incr; the reverse sweep then
-// runs in the opposite order of the forward dataflow, one thread per cell (per cell
-// and target family in k_adj_points).  The
-// reverse of a gather stencil is a scatter: every block accumulates its scattered
-// contributions in an LDS window over its cells plus the reach of the stencil
-// (LDS FP64 atomics), then adds the window to global memory once (one global
-// atomic per window entry instead of one per contribution):
+// cot_n = (d step / d state_n)^T cot_np1 at fixed dt, in three kernels.  The reverse
+// of a gather stencil is a scatter: every block accumulates its scattered
+// contributions in an LDS window over its cells plus the reach of the stencil (LDS
+// FP64 atomics), then adds the window to global memory once (one global atomic per
+// window entry instead of one per contribution):
+//   k_adj_fwd      forward intermediates recomputed from state_n (recovered centres
+//                  W^C, node increments of both durations); zeroes the accumulation
+//                  planes and starts the averages' cotangent at cot_np1's.
 //   k_adj_points   average update and space-time Simpson fluxes (transposed), then
-//                  for every target and duration the transposed transported point
-//                  update: density closure, Q2 evaluation of W and of the increments
-//                  at the foot (values and foot position), the two Picard stages.
-//                  Scatters into cot_n (point planes), lambda_C and lambda_D.
-//   k_adj_incr     transposed node increments: Horner in r, freezing
-//                  (c_K = sqrt(gamma p / rho), Z = rho c), transposed monomial blocks
-//                  and Lagrange-to-monomial transforms of every wedge.
-//   k_adj_centre   transposed centre recovery (prim(U_c), inverse Simpson, U(W) at
-//                  the eight boundary nodes); writes the average planes of cot_n.
+//                  for every target and duration the transposed point update (TAI:
+//                  density closure, Q2 evaluation of W and of the increments at the
+//                  foot, values and foot position, the two Picard stages; RB: Q2 of W
+//                  at the foot, the target's own increments).  Scatters into cot_n
+//                  (point planes), lambda_C and lambda_D.
+//   k_adj_incr     transposed node increments (Horner in r, freezing c_K, Z_K,
+//                  transposed monomial blocks and Lagrange-to-monomial transforms of
+//                  every wedge), then the transposed centre recovery (prim(U_c),
+//                  inverse Simpson, U(W) at the eight boundary nodes) applied to each
+//                  block's own share of lambda_C; scatters into the point and average
+//                  planes of cot_n.
 // The floor() that locates a foot is piecewise constant: its derivative is zero
 // (the usual convention; the step is continuous across faces because R_h and I_h are).
 #include <hip/hip_runtime.h>
@@ -323,8 +324,9 @@ __device__ void point_update_adj(const S_& S, const O_& O, int t, int i, int j, 
 // sweep: the tile's primitive node values (node-cells [-1, T+1)) and recovered centres
 // (cells [-1, T)) staged in LDS, then the increments of both durations at the tile's
 // own node-cells (every wedge of a node-cell in [0, T) lies in cells [-1, T)).  Writes
-// W^C of the tile's cells and the 24 increment planes, and zeroes the tile's cells of
-// the planes the reverse sweep accumulates into.
+// W^C of the tile's cells and the 24 increment planes, zeroes the tile's cells of the
+// planes the reverse sweep accumulates into, and starts the averages' cotangent at
+// cot_np1's (the averages enter the new averages with unit weight).
 template <int TX, int TY>
 struct IntTile {
     static constexpr int PX = TX + 2, PY = TY + 2, CX = TX + 1, CY = TY + 1;
@@ -346,9 +348,11 @@ constexpr int kFBX = 32, kFBY = 8, kFNT = kFBX * kFBY;
 using FwdTile = IntTile<kFBX, kFBY>;
 
 // two workgroups per CU (256 registers per lane)
+struct AvgPlanes { const double* src[4]; double* dst[4]; };
+
 __global__ void __launch_bounds__(kFNT, 2) k_adj_fwd(StatePtrs<double> prim, double* C, double* D, PlaneList Z,
-                                                     int nzero, int nx, int ny, double gamma, double lam0,
-                                                     double lam1, unsigned* status) {
+                                                     int nzero, AvgPlanes avg, int nx, int ny, double gamma,
+                                                     double lam0, double lam1, unsigned* status) {
     __shared__ FwdTile L;
     const int i0 = blockIdx.x * kFBX, j0 = blockIdx.y * kFBY, tid = threadIdx.x;
     const size_t N = (size_t)nx * ny;
@@ -377,8 +381,11 @@ __global__ void __launch_bounds__(kFNT, 2) k_adj_fwd(StatePtrs<double> prim, dou
                 for (int q = 0; q < 12; ++q) L.P[q][e / FwdTile::PX][e % FwdTile::PX] = v[r][q];
         }
     }
-    if (own)
+    if (own) {
         for (int q = 0; q < nzero; ++q) Z.p[q][g] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) avg.dst[q][g] = avg.src[q][g];
+    }
     __syncthreads();
     // recovered centres of cells [-1, T)
     {
@@ -684,35 +691,6 @@ __device__ void incr_adj(const AdjNodes& A, const O_& O, const double* lD, int i
     }
 }
 
-// Transposed node increments for a BX x BY block of node-cells; every wedge's cell
-// lies in [-1, B] and its nodes in node-cells [-1, B + 1): the LDS window
-// (point-value and centre planes).
-constexpr int kIBX = 32, kIBY = 8;
-using IncrWin = LdsWin<16, kIBX + 2, kIBY + 2>;
-
-__global__ void __launch_bounds__(kIBX * kIBY) k_adj_incr(StatePtrs<double> prim, const double* C, const double* lD,
-                                                          PlaneList G, int nx, int ny, double gamma, double lam0,
-                                                          double lam1) {
-    __shared__ double win[16 * (kIBX + 2) * (kIBY + 2)];
-    const int i0 = blockIdx.x * kIBX, j0 = blockIdx.y * kIBY;
-    const IncrWin O{win, i0 - 1, j0 - 1};
-    O.zero();
-    __syncthreads();
-    const int i = i0 + (int)threadIdx.x % kIBX;
-    const int j = j0 + (int)threadIdx.x / kIBX;
-    if (i < nx && j < ny) {
-        AdjNodes A{{}, C, nx, ny};
-#pragma unroll
-        for (int k = 0; k < 16; ++k) A.s[k] = prim.p[k];
-        incr_adj<F_V>(A, O, lD, i, j, gamma, lam0, lam1);
-        incr_adj<F_EV>(A, O, lD, i, j, gamma, lam0, lam1);
-        incr_adj<F_EH>(A, O, lD, i, j, gamma, lam0, lam1);
-        incr_adj<F_C>(A, O, lD, i, j, gamma, lam0, lam1);
-    }
-    __syncthreads();
-    flush_window(O, G, nx, ny);
-}
-
 __device__ __forceinline__ void cons_T(const Prim<double>& w, double gamma, const double lU[4], double g[4]) {
     // U = (rho, rho u, rho v, p/(gamma-1) + rho (u^2+v^2)/2)
     const double q2 = 0.5 * (w.u * w.u + w.v * w.v);
@@ -722,50 +700,90 @@ __device__ __forceinline__ void cons_T(const Prim<double>& w, double gamma, cons
     g[3] = lU[3] / (gamma - 1.0);
 }
 
-// Transposed centre recovery for a BX x BY block of cells: writes the average planes
-// of cot_n and scatters into the point values of each cell's eight boundary nodes
-// (node-cells [0, B + 1): the LDS window).
-constexpr int kCBX = 32, kCBY = 8;
-using CentreWin = LdsWin<12, kCBX + 1, kCBY + 1>;
+// Transposed centre recovery of cell (i, j) for the centre cotangent lW: the averages'
+// cotangent (plane 16 + k of the window, weight 9/4) and the point values of the cell's
+// eight boundary nodes (through U(W) at corners, weight -1/16, and edge midpoints, -1/4).
+template <class O_>
+__device__ __forceinline__ void centre_adj(const AdjNodes& A, const O_& O, int i, int j, const double lW[4],
+                                           double gamma) {
+    const Prim<double> Wc = A.node(F_C, i, j);
+    // W = prim(U_c): rho = U0, u = U1/U0, v = U2/U0, p = (g-1)(U3 - (U1 u + U2 v)/2)
+    const double ir = 1.0 / Wc.r, gm1 = gamma - 1.0;
+    double lU[4];
+    lU[0] = lW[0] - lW[1] * Wc.u * ir - lW[2] * Wc.v * ir + lW[3] * gm1 * 0.5 * (Wc.u * Wc.u + Wc.v * Wc.v);
+    lU[1] = lW[1] * ir - lW[3] * gm1 * Wc.u;
+    lU[2] = lW[2] * ir - lW[3] * gm1 * Wc.v;
+    lU[3] = lW[3] * gm1;
+    // U_c = 9/4 [Ubar - sum_corners U / 36 - sum_edges U / 9]
+    const int wb = O.base(i, j);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) O.addb(16 + k, wb, 0, 2.25 * lU[k]);
+    double lc[4], le[4], g[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { lc[k] = -lU[k] * (1.0 / 16.0); le[k] = -lU[k] * 0.25; }
+    cons_T(A.node(F_V, i, j), gamma, lc, g);          O.node(F_V, i, j, g);
+    cons_T(A.node(F_V, i + 1, j), gamma, lc, g);      O.node(F_V, i + 1, j, g);
+    cons_T(A.node(F_V, i, j + 1), gamma, lc, g);      O.node(F_V, i, j + 1, g);
+    cons_T(A.node(F_V, i + 1, j + 1), gamma, lc, g);  O.node(F_V, i + 1, j + 1, g);
+    cons_T(A.node(F_EH, i, j), gamma, le, g);         O.node(F_EH, i, j, g);
+    cons_T(A.node(F_EH, i, j + 1), gamma, le, g);     O.node(F_EH, i, j + 1, g);
+    cons_T(A.node(F_EV, i, j), gamma, le, g);         O.node(F_EV, i, j, g);
+    cons_T(A.node(F_EV, i + 1, j), gamma, le, g);     O.node(F_EV, i + 1, j, g);
+}
 
-__global__ void __launch_bounds__(kCBX * kCBY) k_adj_centre(StatePtrs<double> prim, const double* C, const double* lC,
-                                                            StatePtrs<double> cot1, StatePtrs<double> cot0,
-                                                            PlaneList G, int nx, int ny, double gamma) {
-    __shared__ double win[12 * (kCBX + 1) * (kCBY + 1)];
-    const int i0 = blockIdx.x * kCBX, j0 = blockIdx.y * kCBY;
-    const CentreWin O{win, i0, j0};
+// Transposed node increments and centre recovery for a BX x BY block of node-cells.
+// Every wedge of a node-cell in [0, B) lies in cells [-1, B) and its nodes in node-cells
+// [-1, B + 1): an LDS window over those node-cells collects the point-value, centre and
+// averages' contributions.  The centre recovery is linear in the centre cotangent, so
+// the block applies its transpose to the centre contributions of its own increments
+// (window cells [-1, B)) plus, for its own cells, the centre cotangent the point kernel
+// left in global memory; the neighbouring blocks do the same with theirs, and the sum
+// is the transpose applied to the total.  The centre nodes of those cells and their
+// boundary nodes stay inside the window.
+constexpr int kIBX = 32, kIBY = 8;
+using IncrWin = LdsWin<20, kIBX + 2, kIBY + 2>;   // planes 0..15 as the point window, 16..19 averages
+
+__global__ void __launch_bounds__(kIBX * kIBY) k_adj_incr(StatePtrs<double> prim, const double* C, const double* lD,
+                                                          const double* lC, PlaneList G, int nx, int ny,
+                                                          double gamma, double lam0, double lam1) {
+    __shared__ double win[20 * (kIBX + 2) * (kIBY + 2)];
+    const int i0 = blockIdx.x * kIBX, j0 = blockIdx.y * kIBY;
+    const IncrWin O{win, i0 - 1, j0 - 1};
     O.zero();
     __syncthreads();
-    const int i = i0 + (int)threadIdx.x % kCBX;
-    const int j = j0 + (int)threadIdx.x / kCBX;
-    if (i < nx && j < ny) {
-        AdjNodes A{{}, C, nx, ny};
+    AdjNodes A{{}, C, nx, ny};
 #pragma unroll
-        for (int k = 0; k < 16; ++k) A.s[k] = prim.p[k];
-        const size_t N = (size_t)nx * ny, c = A.idx(i, j);
-        const double lW[4] = {lC[c], lC[N + c], lC[2 * N + c], lC[3 * N + c]};
-        const Prim<double> Wc = A.node(F_C, i, j);
-        // W = prim(U_c): rho = U0, u = U1/U0, v = U2/U0, p = (g-1)(U3 - (U1 u + U2 v)/2)
-        const double ir = 1.0 / Wc.r, gm1 = gamma - 1.0;
-        double lU[4];
-        lU[0] = lW[0] - lW[1] * Wc.u * ir - lW[2] * Wc.v * ir + lW[3] * gm1 * 0.5 * (Wc.u * Wc.u + Wc.v * Wc.v);
-        lU[1] = lW[1] * ir - lW[3] * gm1 * Wc.u;
-        lU[2] = lW[2] * ir - lW[3] * gm1 * Wc.v;
-        lU[3] = lW[3] * gm1;
-        // U_c = 9/4 [Ubar - sum_corners U / 36 - sum_edges U / 9]
+    for (int k = 0; k < 16; ++k) A.s[k] = prim.p[k];
+    {
+        const int i = i0 + (int)threadIdx.x % kIBX;
+        const int j = j0 + (int)threadIdx.x / kIBX;
+        if (i < nx && j < ny) {
+            incr_adj<F_V>(A, O, lD, i, j, gamma, lam0, lam1);
+            incr_adj<F_EV>(A, O, lD, i, j, gamma, lam0, lam1);
+            incr_adj<F_EH>(A, O, lD, i, j, gamma, lam0, lam1);
+            incr_adj<F_C>(A, O, lD, i, j, gamma, lam0, lam1);
+        }
+    }
+    __syncthreads();
+    // cells [-1, B): each centre entry is read (and cleared, so that the flush skips it)
+    // by one thread, which scatters into other planes only
+    const size_t N = (size_t)nx * ny;
+    constexpr int CW = kIBX + 1, CH = kIBY + 1;
+    for (int e = threadIdx.x; e < CW * CH; e += blockDim.x) {
+        const int i = i0 - 1 + e % CW, j = j0 - 1 + e / CW;
+        // past a ragged grid edge the window holds no contributions (the block's
+        // node-cells there are skipped), and the cell would index outside the grid
+        if (i >= nx || j >= ny) continue;
+        const bool own = i >= i0 && j >= j0 && i < nx && j < ny;
+        const int wb = O.base(i, j);
+        double lW[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) cot0.p[k][c] = cot1.p[k][c] + 2.25 * lU[k];
-        double lc[4], le[4], g[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) { lc[k] = -lU[k] * (1.0 / 16.0); le[k] = -lU[k] * 0.25; }
-        cons_T(A.node(F_V, i, j), gamma, lc, g);          O.node(F_V, i, j, g);
-        cons_T(A.node(F_V, i + 1, j), gamma, lc, g);      O.node(F_V, i + 1, j, g);
-        cons_T(A.node(F_V, i, j + 1), gamma, lc, g);      O.node(F_V, i, j + 1, g);
-        cons_T(A.node(F_V, i + 1, j + 1), gamma, lc, g);  O.node(F_V, i + 1, j + 1, g);
-        cons_T(A.node(F_EH, i, j), gamma, le, g);         O.node(F_EH, i, j, g);
-        cons_T(A.node(F_EH, i, j + 1), gamma, le, g);     O.node(F_EH, i, j + 1, g);
-        cons_T(A.node(F_EV, i, j), gamma, le, g);         O.node(F_EV, i, j, g);
-        cons_T(A.node(F_EV, i + 1, j), gamma, le, g);     O.node(F_EV, i + 1, j, g);
+        for (int k = 0; k < 4; ++k) {
+            double* c = O.a + wb + (12 + k) * IncrWin::kPlane;
+            lW[k] = *c + (own ? lC[k * N + (size_t)j * nx + i] : 0.0);
+            *c = 0.0;
+        }
+        centre_adj(A, O, i, j, lW, gamma);
     }
     __syncthreads();
     flush_window(O, G, nx, ny);
@@ -789,11 +807,15 @@ hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1_[16], vo
     for (int k = 0; k < 4; ++k) L.p[np++] = lC + k * N;
     for (int k = 0; k < 24; ++k) L.p[np++] = lD + k * N;
     // L lists the window planes in LdsWin order: point values, centres, increments
+    PlaneList Li = L;   // k_adj_incr's window: point values, centres (consumed in the block), averages
+    for (int k = 0; k < 4; ++k) Li.p[16 + k] = cot0.p[k];
+    AvgPlanes avg;
+    for (int k = 0; k < 4; ++k) { avg.src[k] = cot1.p[k]; avg.dst[k] = cot0.p[k]; }
     const double lam1 = a.dt / a.h, lam0 = 0.5 * lam1;
     {
         dim3 grd((a.nx + kFBX - 1) / kFBX, (a.ny + kFBY - 1) / kFBY);
-        hipLaunchKernelGGL(k_adj_fwd, grd, dim3(kFNT), 0, a.stream, prim, C, Dfwd, L, np, a.nx, a.ny, a.gamma, lam0,
-                           lam1, a.status);
+        hipLaunchKernelGGL(k_adj_fwd, grd, dim3(kFNT), 0, a.stream, prim, C, Dfwd, L, np, avg, a.nx, a.ny, a.gamma,
+                           lam0, lam1, a.status);
     }
     if (a.ev_begin) (void)hipEventRecord(a.ev_begin, a.stream);
     {
@@ -808,13 +830,8 @@ hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1_[16], vo
     }
     {
         dim3 grd((a.nx + kIBX - 1) / kIBX, (a.ny + kIBY - 1) / kIBY);
-        hipLaunchKernelGGL(k_adj_incr, grd, dim3(kIBX * kIBY), 0, a.stream, prim, C, lD, L, a.nx, a.ny, a.gamma,
+        hipLaunchKernelGGL(k_adj_incr, grd, dim3(kIBX * kIBY), 0, a.stream, prim, C, lD, lC, Li, a.nx, a.ny, a.gamma,
                            lam0, lam1);
-    }
-    {
-        dim3 grd((a.nx + kCBX - 1) / kCBX, (a.ny + kCBY - 1) / kCBY);
-        hipLaunchKernelGGL(k_adj_centre, grd, dim3(kCBX * kCBY), 0, a.stream, prim, C, lC, cot1, cot0, L, a.nx,
-                           a.ny, a.gamma);
     }
     if (a.ev_end) (void)hipEventRecord(a.ev_end, a.stream);
     return hipGetLastError();
