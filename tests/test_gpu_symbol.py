@@ -1,0 +1,143 @@
+"""The GPU step's linearisation against the Fourier symbol of Sec. 5.
+
+About the uniform background of Sec. 5 (rho0 = p0 = 1, |u0| = 0.2 at 25 degrees), one
+FP64 GPU step of background +- eps Re(q e^{i(xi i + eta j)}) and of the sine mode gives,
+by central differences, the complexified linear response G(xi, eta) q e^{i(xi i + eta j)}
+to O(eps^2).  It must equal the oracle's symbol (oracle/symbol.py: 16x16 amplification
+matrix, every family as primitive perturbations), which is pinned to the printed
+pressure-gain errors and stability limits of Sec. 5 (tests/test_symbol.py).  The
+average planes are conservative on the GPU: perturbations enter through dU/dW at the
+background and responses are mapped back with its inverse.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 1.4
+N = 44           # 2 pi * 7 / 44 = 0.9996: wave vectors with |k h| close to 1 are on the lattice
+EPS = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+def _dUdW(W0):
+    r, u, v, p = W0
+    return np.array([[1, 0, 0, 0], [u, r, 0, 0], [v, 0, r, 0], [0.5 * (u * u + v * v), r * u, r * v, 1 / (GAMMA - 1)]])
+
+
+def _background(W0):
+    r, u, v, p = W0
+    U = (r, r * u, r * v, p / (GAMMA - 1) + 0.5 * r * (u * u + v * v))
+    s = np.empty((16, N, N))
+    for k in range(4):
+        s[k] = U[k]
+        for f in (4, 8, 12):
+            s[f + k] = W0[k]
+    return s
+
+
+def _planes(qc, M):
+    """Complex mode planes: family f, variable v at cell (i, j) = q[4f + v] e^{i(xi i + eta j)};
+    the average family converted to conservative perturbations."""
+    q, xi, eta = qc
+    i = np.arange(N)
+    ph = np.exp(1j * (xi * i[None, :] + eta * i[:, None]))       # [j][i]
+    out = np.empty((16, N, N), complex)
+    qa = M @ q[0:4]
+    for k in range(4):
+        out[k] = qa[k] * ph
+        for f in (1, 2, 3):
+            out[4 * f + k] = q[4 * f + k] * ph
+    return out, ph
+
+
+def gpu_response(torch_dev, st, s0, dt, z):
+    """Complexified linear response of one step to the complex perturbation planes z."""
+    torch, dev = torch_dev
+    res = []
+    for part in (z.real, z.imag):
+        outs = []
+        for sgn in (1.0, -1.0):
+            x = torch.from_numpy(s0 + sgn * EPS * part).to(dev)
+            st.step(x, dt, 1)
+            outs.append(x.cpu().numpy())
+        res.append((outs[0] - outs[1]) / (2 * EPS))
+    return res[0] + 1j * res[1]
+
+
+@pytest.mark.parametrize("method", ["TAI", "RB"])
+def test_gpu_symbol(torch_dev, method):
+    torch, dev = torch_dev
+    from oracle.symbol import Symbol
+    from paper_2605_12915_amd.stepper import Stepper
+    sym = Symbol(gamma=GAMMA)
+    W0 = (sym.rho0, sym.u0, sym.v0, sym.p0)
+    M = _dUdW(W0)
+    Minv = np.linalg.inv(M)
+    s0 = _background(W0)
+    h = 1.0 / N
+    st = Stepper(N, N, h, GAMMA, scheme=method.lower(), device=dev)
+    rng = np.random.default_rng(11)
+    nus = (0.1, 0.19) if method == "RB" else (0.2, 0.3, 0.4, 0.5)
+    worst = 0.0
+    for nu in nus:
+        dt = nu * h / sym.c0                        # nu = c0 dt / h (Sec. 5)
+        for mx, my in ((7, 0), (5, 5), (6, -3), (-2, 7), (3, 1), (0, 0)):
+            xi, eta = 2 * math.pi * mx / N, 2 * math.pi * my / N
+            G = sym.G(method, nu, xi, eta)
+            for q in (rng.normal(size=16) + 1j * rng.normal(size=16),
+                      sym.acoustic_mode(xi, eta, +1) if (mx, my) != (0, 0) else np.ones(16, complex)):
+                z, ph = _planes((q, xi, eta), M)
+                R = gpu_response(torch_dev, st, s0, dt, z)
+                want = G @ q
+                got = np.empty((16, N, N), complex)
+                got[0:4] = np.einsum("kl,lji->kji", Minv, R[0:4])
+                got[4:] = R[4:]
+                err = float(np.abs(got - want[:, None, None] * ph[None]).max()) / float(np.abs(want).max())
+                worst = max(worst, err)
+                assert err < 1e-8, (method, nu, mx, my, err)
+    print(method, "GPU linear response vs symbol: worst relative error", worst)
+
+
+def test_gpu_pressure_gain_near_printed(torch_dev):
+    """Sec. 5.3: the TAI pressure gain of the acoustic mode at |k h| ~ 1, measured on the
+    GPU, against the exact gain.  The printed maxima over the wave-vector angle at
+    |k h| = 1 are 8.48e-3, 8.75e-3, 7.02e-3, 5.15e-3 (nu = 0.2 ... 0.5), attained along
+    the grid axes, where the lattice has |k h| = 2 pi 7 / 44 = 0.9996: the largest error
+    over the sampled angles must match the printed value to its last digit (half a unit,
+    5e-6, plus the small |k h| offset)."""
+    torch, dev = torch_dev
+    from oracle.symbol import Symbol
+    from paper_2605_12915_amd.stepper import Stepper
+    sym = Symbol(gamma=GAMMA)
+    W0 = (sym.rho0, sym.u0, sym.v0, sym.p0)
+    M = _dUdW(W0)
+    s0 = _background(W0)
+    h = 1.0 / N
+    st = Stepper(N, N, h, GAMMA, device=dev)
+    printed = {0.2: 8.48e-3, 0.3: 8.75e-3, 0.4: 7.02e-3, 0.5: 5.15e-3}
+    lattice = [(7, 0), (0, 7), (-7, 0), (0, -7), (5, 5), (-5, 5), (-5, -5), (5, -5)]
+    for nu, pmax in printed.items():
+        dt = nu * h / sym.c0
+        errs = []
+        for mx, my in lattice:
+            xi, eta = 2 * math.pi * mx / N, 2 * math.pi * my / N
+            q = sym.acoustic_mode(xi, eta, +1)
+            z, ph = _planes((q, xi, eta), M)
+            R = gpu_response(torch_dev, st, s0, dt, z)
+            g = R[11] / (q[11] * ph)                  # Ev pressure
+            assert float(np.abs(g - g.mean()).max()) < 1e-8   # one gain for every cell
+            g = complex(g.mean())
+            errs.append(abs(g - sym.exact_gain(xi, eta, nu)))
+            assert abs(g - sym.pressure_gain("TAI", math.hypot(xi, eta), math.atan2(eta, xi), nu)) < 1e-9
+        print("nu", nu, "GPU pressure-gain errors at |k h| ~ 1:", ["%.3e" % e for e in errs], "printed max", pmax)
+        assert abs(max(errs) - pmax) < 2e-5, (nu, max(errs), pmax)
