@@ -77,8 +77,16 @@ def cpu_baseline(n: int, steps: int, P=None, s=None):
     t0 = time.perf_counter()
     ref.run(s, P.h, P.gamma, dt, steps, threads=threads)
     el = time.perf_counter() - t0
+    # one thread, on a 256^2 grid of the same flow (a second or two)
+    Q = I.fourier_modes(256)
+    q = Q.state()
+    t1 = time.perf_counter()
+    ref.run(q, Q.h, Q.gamma, Q.dt_for_cfl(0.4), 2, threads=1)
+    el1 = time.perf_counter() - t1
     return {"value": n * n * steps / el / 1e6, "unit": "Mcell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n}x{n} Fourier-mode flow, {steps} steps, FP64, {threads} OpenMP threads, {el:.2f} s"}
+            "sample": f"{n}x{n} Fourier-mode flow, {steps} steps, FP64, {threads} OpenMP threads, {el:.2f} s",
+            "single_thread_value": 256 * 256 * 2 / el1 / 1e6,
+            "single_thread_sample": f"256x256, 2 steps, 1 thread, {el1:.2f} s"}
 
 
 def timed(torch, fn):
@@ -331,6 +339,13 @@ def main():
     t_alu = flops / (perf.FP64_PEAK_TFLOPS * 1e12)
     t_hbm = perf.ALGO_BYTES_PER_CELL_F64 * ncell / (perf.HBM_PEAK_GBS * 1e9)
     tr = perf.stored_traffic(kname)
+    # measured copy bandwidth: a plain 1 GiB device-to-device copy (read + write 2 GiB)
+    src = torch.empty(128 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    copy_s = min(timed(torch, lambda: dst.copy_(src)) for _ in range(5))
+    copy_gbs = 2 * src.numel() * 8 / copy_s / 1e9
+    del src, dst
     log(f"headline: {value:.0f} Mcell/s, kernel {ker_ms:.3f} ms")
     line = {
         "metric": "Mcell-updates/s per AF step (FP64 vs FP32) at stated error; adjoint/forward ratio",
@@ -346,11 +361,20 @@ def main():
                      "algo_flops_per_cell": perf.ALGO_FLOPS_PER_CELL_F64,
                      "algo_bytes_per_cell": perf.ALGO_BYTES_PER_CELL_F64,
                      "hbm_gbs_algorithmic": perf.ALGO_BYTES_PER_CELL_F64 * ncell / (ker_ms * 1e-3) / 1e9,
-                     "t_alu_ms": t_alu * 1e3, "t_hbm_ms": t_hbm * 1e3},
+                     "t_alu_ms": t_alu * 1e3, "t_hbm_ms": t_hbm * 1e3,
+                     "copy_gbs_measured": copy_gbs},
         "finite": ok,
         "diagnostics_ms": diag_ms,
         "value_with_diagnostics_every_step": ncell * args.steps / (el + args.steps * diag_ms * 1e-3) / 1e6,
     }
+    if tr:
+        # the counters' view of the same kernel: HBM bytes and executed FP64 flops per launch
+        gbs = tr["traffic_bytes_per_launch"] / (ker_ms * 1e-3) / 1e9
+        line["roofline"].update({"traffic_gbs": gbs, "traffic_frac_of_peak": gbs / perf.HBM_PEAK_GBS,
+                                 "traffic_frac_of_copy": gbs / copy_gbs})
+        if tr.get("executed_fp64_flops_per_launch"):
+            ex = tr["executed_fp64_flops_per_launch"] / (ker_ms * 1e-3) / 1e12
+            line["roofline"].update({"executed_tflops": ex, "executed_frac_of_peak": ex / perf.FP64_PEAK_TFLOPS})
     st.close()
     del x
     torch.cuda.empty_cache()
