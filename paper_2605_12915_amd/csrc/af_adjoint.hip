@@ -515,8 +515,10 @@ using PointStage = StageWin<kPRX, kPRY>;
 constexpr size_t kPointLds = sizeof(double) * 2 * 40 * kPWin;   // staged state + accumulators
 static_assert(kPWin <= kPNT, "one staging round");
 
+// (registers bounded for 2 waves per SIMD: the workgroup alone would let the compiler
+// take accumulation registers too, and the RB instantiation did, at one wave per SIMD)
 template <int SCHEME>
-__global__ void __launch_bounds__(kPNT) k_adj_points(StatePtrs<double> prim, const double* C, const double* Dfwd,
+__global__ void __launch_bounds__(kPNT, 2) k_adj_points(StatePtrs<double> prim, const double* C, const double* Dfwd,
                                                      StatePtrs<double> cot1, PlaneList G, int nx, int ny,
                                                      double gamma, double lam0, double lam1) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -746,7 +748,7 @@ __device__ __forceinline__ void centre_adj(const AdjNodes& A, const O_& O, int i
 constexpr int kIBX = 32, kIBY = 8;
 using IncrWin = LdsWin<20, kIBX + 2, kIBY + 2>;   // planes 0..15 as the point window, 16..19 averages
 
-__global__ void __launch_bounds__(kIBX * kIBY) k_adj_incr(StatePtrs<double> prim, const double* C, const double* lD,
+__global__ void __launch_bounds__(kIBX * kIBY, 2) k_adj_incr(StatePtrs<double> prim, const double* C, const double* lD,
                                                           const double* lC, PlaneList G, int nx, int ny,
                                                           double gamma, double lam0, double lam1) {
     __shared__ double win[20 * (kIBX + 2) * (kIBY + 2)];

@@ -33,7 +33,10 @@ def gpu_adjoint(torch_dev, P, s0, lam, dt, scheme="tai"):
     return g.cpu().numpy()
 
 
-@pytest.mark.parametrize("nx,ny,seed,scheme", [(6, 5, 1, "tai"), (7, 8, 2, "tai"), (6, 5, 3, "rb"), (7, 8, 4, "rb")])
+# tiny grids (windows wrapping onto themselves) and ragged ones (17: a node-cell covered by
+# three point blocks' windows across the periodic seam)
+@pytest.mark.parametrize("nx,ny,seed,scheme", [(6, 5, 1, "tai"), (7, 8, 2, "tai"), (6, 5, 3, "rb"), (7, 8, 4, "rb"),
+                                               (13, 11, 5, "tai"), (17, 12, 6, "tai"), (17, 12, 7, "rb")])
 def test_adjoint_exact_vs_oracle_jacobian(torch_dev, orc, nx, ny, seed, scheme):
     P = I.random_smooth(nx, ny, seed=seed, amp=0.15, vel=(0.35, -0.25))
     s0 = P.state()
