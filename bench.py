@@ -113,8 +113,8 @@ def form_fp32(torch, dev, n, steps):
     from paper_2605_12915_amd import perf
     from paper_2605_12915_amd.stepper import Stepper, to_perturbation
     out = {}
-    for tag, P in (("3a_isentropic_vortex", I.isentropic_vortex(n, uinf=(1.0, 1.0))),
-                   ("3b_gaussian_pulse", I.gaussian_pulse(n, amp=0.1, width=0.05))):
+    for tag, P in (("isentropic_vortex", I.isentropic_vortex(n, uinf=(1.0, 1.0))),
+                   ("gaussian_pulse", I.gaussian_pulse(n, amp=0.1, width=0.05))):
         log(f"fp32 {tag}: generating {n}x{n} input")
         s0 = P.state()
         dt = P.dt_for_cfl(0.4)
@@ -391,7 +391,7 @@ def main():
     big32 = None
     if "fp32" in forms:
         line["forms"]["fp32"] = form_fp32(torch, dev, args.fp32_n, args.fp32_steps)
-        big32 = line["forms"]["fp32"]["3b_gaussian_pulse"]["value"]
+        big32 = line["forms"]["fp32"]["gaussian_pulse"]["value"]
     if "adjoint" in forms:
         line["forms"]["adjoint"] = form_adjoint(torch, dev, args.adj_n, args.adj_steps)
     if "batch" in forms:

@@ -111,7 +111,7 @@ def test_rollout_gradient_vs_fd(torch_dev):
         assert rel < 1e-6
 
 
-def test_adjoint_config4_full_size_dot_product(torch_dev, orc):
+def test_adjoint_pulse_512_dot_product(torch_dev, orc):
     """512^2 acoustic pulse of the gradient benchmark: <lambda, J v> from the oracle's
     complex-step JVP equals <J^T lambda, v> from the GPU adjoint."""
     P = I.acoustic_pulse_adjoint(512)
@@ -123,5 +123,5 @@ def test_adjoint_config4_full_size_dot_product(torch_dev, orc):
     _, jv = orc.step_jvp(s0, v, P.h, P.gamma, dt)
     lhs = float(np.sum(lam * jv))
     rhs = float(np.sum(gpu_adjoint(torch_dev, P, s0, lam, dt) * v))
-    print("config 4 dot product", lhs, rhs)
+    print("512^2 pulse dot product", lhs, rhs)
     assert abs(lhs - rhs) <= 1e-10 * np.sqrt(np.sum(lam ** 2) * np.sum(jv ** 2))

@@ -206,7 +206,7 @@ def test_batch_errors(torch_dev):
         b.step(xs[:2], dts[:2], 1)
 
 
-def test_batch_config5_full_size_one_step(torch_dev, orc):
+def test_batch_64_grids_full_size_one_step(torch_dev, orc):
     """The benchmark's batch (64 double shear layers, sizes N in [32, 1024]) in the
     tuned launch configuration, one step, every grid against the oracle."""
     torch, dev = torch_dev
@@ -220,7 +220,7 @@ def test_batch_config5_full_size_one_step(torch_dev, orc):
     b = Batch(grids_of(Ps), check_errors=True, device=dev)
     b.step(xs, dts, 1)
     torch.cuda.synchronize()
-    print("config 5 tuned tile", b.info()["chosen"], b.info()["mode"], flush=True)
+    print("64-grid batch: tuned tile", b.info()["chosen"], b.info()["mode"], flush=True)
     worst = 0.0
     for P, s, x, dt in zip(Ps, s0, xs, dts):
         want = orc.step(s, P.h, P.gamma, dt)
@@ -229,4 +229,4 @@ def test_batch_config5_full_size_one_step(torch_dev, orc):
         tol = f32_tolerance(want, s, P.bg, P.gamma, 1)
         worst = max(worst, float((err / tol).max()))
         assert np.all(err <= tol), (P.nx, np.array2string(err / tol, precision=2))
-    print("config 5 worst err/tol", worst)
+    print("64-grid batch: worst err/tol", worst)

@@ -105,7 +105,7 @@ def test_f32_diagnostics(torch_dev, orc):
         assert abs(got[k] - v) <= 1e-6 * max(1.0, abs(v)), (k, got[k], v)
 
 
-def test_f32_config3_full_size_one_step(torch_dev, orc):
+def test_f32_4096_states_one_step(torch_dev, orc):
     """4096^2 (both sub-cases of the FP32 benchmark), one step from the same state:
     every output against the oracle at the FP32 form's bound (the oracle runs the full
     grid on the host cores)."""

@@ -37,12 +37,12 @@ def _run_gpu(torch_dev, P, s0, dt, n, **kw):
     return x.cpu().numpy(), st
 
 
-def test_config1_vortex_100_steps(torch_dev, orc):
+def test_vortex_64_100_steps(torch_dev, orc):
     """Isentropic vortex on [0,10]^2, 64^2, mean flow (1,1), CFL 0.3, 100 steps."""
     P = I.isentropic_vortex(64, uinf=(1.0, 1.0))
     s0 = P.state()
     dt = P.dt_for_cfl(0.3)
-    print("config1: 64x64 vortex, dt", dt, flush=True)
+    print("64x64 vortex, dt", dt, flush=True)
     want = orc.run(s0, P.h, P.gamma, dt, 100)
     got, _ = _run_gpu(torch_dev, P, s0, dt, 100, check_errors=True)
     err = _err(got, want)
@@ -133,17 +133,17 @@ def test_diagnostics_match_oracle(torch_dev, orc):
         assert abs(got[k] - v) <= 1e-12 * max(1.0, abs(v)), (k, got[k], v)
 
 
-def test_config2_full_size_one_step(torch_dev, orc):
+def test_fourier_modes_2048_one_step(torch_dev, orc):
     """2048^2 Fourier-mode flow at CFL 0.4: every output of one step against the
     oracle (the oracle runs the full grid on the host cores)."""
     P = I.fourier_modes(2048)
     s0 = P.state()
     dt = P.dt_for_cfl(0.4)
-    print("config2 full size: generating done, oracle step ...", flush=True)
+    print("2048^2 Fourier-mode flow: generating done, oracle step ...", flush=True)
     want = orc.step(s0, P.h, P.gamma, dt)
     got, _ = _run_gpu(torch_dev, P, s0, dt, 1, check_errors=True)
     err = _err(got, want)
-    print("config2 per-plane error", err.max(), flush=True)
+    print("2048^2 per-plane error", err.max(), flush=True)
     assert err.max() <= TOL
 
 
