@@ -24,7 +24,7 @@
 
 namespace af {
 
-// 26x12 cells, 512 threads (146 KB of LDS, one workgroup per CU).  The heavy phases
+// 26x12 cells, 512 threads (156 KB of LDS, one workgroup per CU).  The heavy phases
 // run in whole rounds of 512 threads: phase 2 has 29x15 = 435 node-cells (one round,
 // as the 35x11 of a 32x8 tile, but for 312 owned cells instead of 256) and phase 3
 // 1013 targets (two rounds, 99% filled).  15% faster than 32x8; 28x12 (three phase-3
