@@ -125,3 +125,26 @@ def test_adjoint_pulse_512_dot_product(torch_dev, orc):
     rhs = float(np.sum(gpu_adjoint(torch_dev, P, s0, lam, dt) * v))
     print("512^2 pulse dot product", lhs, rhs)
     assert abs(lhs - rhs) <= 1e-10 * np.sqrt(np.sum(lam ** 2) * np.sum(jv ** 2))
+
+
+@pytest.mark.parametrize("scheme", ["tai", "rb"])
+def test_adjoint_repeated_calls_on_one_context(torch_dev, scheme):
+    """A context's adjoint scratch (recomputed intermediates, reverse accumulators) carries
+    nothing from one call to the next: consecutive calls on one context (different states
+    and cotangents, forward steps in between, a ragged 37 x 29 grid) equal calls on fresh
+    contexts, up to the order of the atomic additions."""
+    torch, dev = torch_dev
+    from paper_2605_12915_amd.stepper import Stepper
+    P = I.random_smooth(37, 29, seed=21, amp=0.15, vel=(0.3, -0.2))
+    dt = P.dt_for_cfl(0.45 if scheme == "tai" else 0.19)
+    rng = np.random.default_rng(22)
+    st = Stepper(P.nx, P.ny, P.h, P.gamma, scheme=scheme, device=dev)
+    x = torch.from_numpy(P.state()).to(dev)
+    for call in range(4):
+        lam = rng.normal(size=P.state().shape) * (10.0 if call % 2 else 1.0)
+        s0 = x.cpu().numpy()
+        got = st.adjoint(x, torch.from_numpy(lam).to(dev), dt).cpu().numpy()
+        want = gpu_adjoint(torch_dev, P, s0, lam, dt, scheme)
+        err = np.abs(got - want).max() / np.abs(want).max()
+        assert err < 1e-13, (call, err)
+        st.step(x, dt, 2)
