@@ -24,6 +24,9 @@ Readings (the paper is garbled or silent here):
     (0,1/2), (1/2,0) in cell units.
   * the exact pressure gain includes the advective phase,
     g_ex = exp(-i [lambda (u0 xi + v0 eta) + s nu kappa]).
+  * the "exact one-step residual" of the refinement study is ||G q - g q|| / ||q|| for
+    the exact mode q, unscaled; the refinement holds K = 1 and T = 1, so h = kappa and
+    N = T / dt = c0 / (nu kappa) steps.
 
 State ordering of q: [avg(rho,u,v,p), V(rho,u,v,p), Ev(...), Eh(...)], every family
 as primitive perturbations.
@@ -250,14 +253,38 @@ class Symbol:
         return np.vstack([Gav, half["V"], half["Ev"], half["Eh"]])
 
     # ---- exact modes --------------------------------------------------------
+    @staticmethod
+    def sample_families(rvec, xi, eta):
+        """16-vector of the mode rvec e^{i k.x}: exact cell average, then the values at
+        V (0, 0), Ev (0, 1/2) and Eh (1/2, 0) in cell units."""
+        avg = _cellavg(xi) * _cellavg(eta)
+        return np.concatenate([avg * rvec, rvec, np.exp(0.5j * eta) * rvec, np.exp(0.5j * xi) * rvec])
+
     def acoustic_mode(self, xi, eta, s=+1):
         """q^ex for the acoustic branch s (mode r_s(k) e^{i k.x})."""
         kap = math.hypot(xi, eta)
         kx, ky = xi / kap, eta / kap
         rvec = np.array([1 / self.c0 ** 2, s * kx / self.Z0, s * ky / self.Z0, 1.0], complex)
-        avg = _cellavg(xi) * _cellavg(eta)
-        q = np.concatenate([avg * rvec, rvec, np.exp(0.5j * eta) * rvec, np.exp(0.5j * xi) * rvec])
-        return q
+        return self.sample_families(rvec, xi, eta)
+
+    BRANCHES = ("entropy", "shear", "acoustic+", "acoustic-")
+
+    def exact_modes(self, xi, eta):
+        """The four exact modes q_j of the linearized Euler equations about W0 (rows, in
+        BRANCHES order): entropy (density only), shear (velocity normal to k), and the two
+        acoustic branches (pressure with the density p/c0^2 and velocity +-k p/Z0)."""
+        kap = math.hypot(xi, eta)
+        kx, ky = xi / kap, eta / kap
+        shear = np.array([0.0, -ky, kx, 0.0], complex)
+        return np.stack([self.sample_families(np.array([1.0, 0, 0, 0], complex), xi, eta),
+                         self.sample_families(shear, xi, eta),
+                         self.acoustic_mode(xi, eta, +1), self.acoustic_mode(xi, eta, -1)])
+
+    def exact_gains(self, xi, eta, nu):
+        """g_j = e^{-i omega_j dt}: advection alone for entropy and shear, advection plus
+        or minus the sound speed for the acoustic branches."""
+        return np.array([self.exact_gain(xi, eta, nu, 0), self.exact_gain(xi, eta, nu, 0),
+                         self.exact_gain(xi, eta, nu, +1), self.exact_gain(xi, eta, nu, -1)])
 
     def exact_gain(self, xi, eta, nu, s=+1):
         lam = nu / self.c0
@@ -274,6 +301,51 @@ class Symbol:
 
 def _cellavg(k):
     return 1.0 if abs(k) < 1e-14 else (np.exp(1j * k) - 1) / (1j * k)
+
+
+# ---------------------------------------------------------------------------
+# Sec. 5: one-step residual, repeated-step error, modal errors
+# ---------------------------------------------------------------------------
+
+def one_step_residual(G, q, g):
+    """||G q - g q|| / ||q|| for the exact mode q with exact gain g."""
+    return float(np.linalg.norm(G @ q - g * q) / np.linalg.norm(q))
+
+
+def repeated_step_error(G, q, g, n):
+    """eq. repeated-error: ||G^n q - g^n q|| / ||q||."""
+    v = q.copy()
+    for _ in range(n):
+        v = G @ v
+    return float(np.linalg.norm(v - g ** n * q) / np.linalg.norm(q))
+
+
+def match_modes(G, Q):
+    """Numerical eigenvalues of G assigned one-to-one to the exact modes (rows of Q) by
+    largest normalized right-eigenvector overlap |q^H v| / (|q| |v|): the largest
+    overlap over unassigned pairs is taken first.  Returns (eigenvalues, overlaps,
+    eigenvector indices)."""
+    w, V = np.linalg.eig(G)
+    O = np.abs(Q.conj() @ V)
+    O /= np.linalg.norm(Q, axis=1)[:, None] * np.linalg.norm(V, axis=0)[None, :]
+    rows, cols = list(range(Q.shape[0])), list(range(V.shape[1]))
+    gt = np.zeros(Q.shape[0], complex)
+    ov = np.zeros(Q.shape[0])
+    idx = np.zeros(Q.shape[0], int)
+    while rows:
+        j, m = max(((j, m) for j in rows for m in cols), key=lambda jm: O[jm])
+        gt[j], ov[j], idx[j] = w[m], O[j, m], m
+        rows.remove(j)
+        cols.remove(m)
+    return gt, ov, idx
+
+
+def modal_errors(sym: Symbol, method: str, nu: float, xi: float, eta: float):
+    """eq. modal-amplitude-phase-errors for the four branches: (eps_A, eps_phi, overlaps)
+    with eps_A = ||g~| - 1| and eps_phi = |arg(g~ / g)|."""
+    gt, ov, _ = match_modes(sym.G(method, nu, xi, eta), sym.exact_modes(xi, eta))
+    g = sym.exact_gains(xi, eta, nu)
+    return np.abs(np.abs(gt) - 1.0), np.abs(np.angle(gt / g)), ov
 
 
 def spectral_radius(sym: Symbol, method: str, nu: float, n: int = 24, kmin=None):

@@ -141,3 +141,66 @@ def test_gpu_pressure_gain_near_printed(torch_dev):
             assert abs(g - sym.pressure_gain("TAI", math.hypot(xi, eta), math.atan2(eta, xi), nu)) < 1e-9
         print("nu", nu, "GPU pressure-gain errors at |k h| ~ 1:", ["%.3e" % e for e in errs], "printed max", pmax)
         assert abs(max(errs) - pmax) < 2e-5, (nu, max(errs), pmax)
+
+
+# ---- full amplification matrix, modal errors and refinement slopes of the GPU step --------
+
+@pytest.mark.parametrize("method", ["TAI", "RB"])
+def test_measured_symbol_equals_oracle(torch_dev, method):
+    """The whole 16x16 G of the GPU step (paper_2605_12915_amd/linear.py, 64 steps per
+    wave vector) equals the oracle's symbol."""
+    from oracle.symbol import Symbol
+    from paper_2605_12915_amd.linear import SymbolMeter, lattice_wavevector
+    sym = Symbol(gamma=GAMMA)
+    m = SymbolMeter(N, N, method.lower(), device=torch_dev[1])
+    worst = 0.0
+    for (mx, my), nu in (((7, 0), 0.25), ((5, 5), 0.19), ((6, -3), 0.4), ((3, 1), 0.1)):
+        if method == "RB" and nu > 0.2:
+            nu = 0.19
+        G = m.measure(mx, my, nu)
+        want = sym.G(method, nu, *lattice_wavevector(N, N, mx, my))
+        err = float(np.abs(G - want).max() / np.abs(want).max())
+        worst = max(worst, err)
+        assert err < 1e-8, (mx, my, nu, err)
+    print(method, "measured G vs symbol: worst relative error", worst)
+
+
+def test_gpu_polar_modal_errors(torch_dev):
+    """Directional modal errors of the GPU step at nu = 0.25 near kappa = pi/4 (eight cells
+    per wavelength), 16 directions: equal to the oracle's at the lattice wave vectors
+    used, and the acoustic phase errors of RB-TAI are below half of RB's (largest and
+    mean over directions), as the directional-error figure of Sec. 5 shows."""
+    from oracle.symbol import Symbol, modal_errors
+    from paper_2605_12915_amd.linear import polar_modal_errors
+    sym = Symbol(gamma=GAMMA)
+    res = {}
+    for method in ("TAI", "RB"):
+        rows = polar_modal_errors(math.pi / 4, 0.25, 16, method.lower(), device=torch_dev[1])
+        for r in rows:
+            a, p, o = modal_errors(sym, method, 0.25, r["xi"], r["eta"])
+            assert np.abs(r["amplitude"] - a).max() < 1e-9, (method, r["theta"])
+            assert np.abs(r["phase"] - p).max() < 1e-9, (method, r["theta"])
+            assert r["overlap"].min() > 0.99
+        res[method] = np.array([r["phase"] for r in rows])
+        print(method, "GPU modal errors, max amplitude", np.array([r["amplitude"] for r in rows]).max(0),
+              "max phase", res[method].max(0))
+    T, R = res["TAI"][:, 2:], res["RB"][:, 2:]
+    assert np.all(T.max(0) < 0.5 * R.max(0)) and np.all(T.mean(0) < 0.5 * R.mean(0))
+
+
+def test_gpu_refinement_slopes(torch_dev):
+    """Sec. 5 refinement at K = 1, T = 1 (h = kappa, N = T / dt steps) on the GPU step's
+    measured G, 128^2 and 256^2 grids, modes along x and along the diagonal: one-step and
+    repeated-step slopes approach three for RB-TAI and for the RB entropy and shear
+    branches, two for the RB acoustic branches."""
+    from paper_2605_12915_amd.linear import refinement_errors
+    for mx, my in ((1, 0), (1, 1)):
+        for method, want in (("tai", (3, 3, 3, 3)), ("rb", (3, 3, 2, 2))):
+            a = refinement_errors(128, mx, my, 0.25, method, device=torch_dev[1])
+            b = refinement_errors(256, mx, my, 0.25, method, device=torch_dev[1])
+            s1 = np.log2(a["one_step"] / b["one_step"]) / math.log2(a["kappa"] / b["kappa"])
+            sN = np.log2(a["repeated"] / b["repeated"]) / math.log2(a["kappa"] / b["kappa"])
+            print(method, (mx, my), "steps", a["steps"], b["steps"], "one-step slopes", np.round(s1, 3),
+                  "repeated-step slopes", np.round(sN, 3))
+            assert np.all(np.abs(s1 - np.array(want)) < 0.1), (method, mx, my, s1)
+            assert np.all(np.abs(sN - np.array(want)) < 0.1), (method, mx, my, sN)

@@ -1,0 +1,76 @@
+"""Host logic of the GPU-step Fourier analysis (paper_2605_12915_amd/linear.py): its exact
+modes, gains, eigenvalue matching and error measures against the oracle's independent
+ones (oracle/symbol.py), applied to the oracle's amplification matrix.  The measurement
+of G itself runs the GPU step (tests/test_gpu_symbol.py)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.symbol import Symbol, match_modes, modal_errors, one_step_residual, repeated_step_error
+from paper_2605_12915_amd import linear as L
+
+
+@pytest.fixture(scope="module")
+def sym():
+    return Symbol()
+
+
+def test_background_and_conversion(sym):
+    assert np.allclose(L.PAPER_BACKGROUND, (sym.rho0, sym.u0, sym.v0, sym.p0), rtol=0, atol=1e-15)
+    W0, g = (1.3, 0.2, -0.1, 0.9), 1.4
+    # dU/dW by central differences of U(W)
+    def U(W):
+        r, u, v, p = W
+        return np.array([r, r * u, r * v, p / (g - 1) + 0.5 * r * (u * u + v * v)])
+    J = np.stack([(U(np.add(W0, e)) - U(np.subtract(W0, e))) / 2e-6 for e in 1e-6 * np.eye(4)], axis=1)
+    assert np.allclose(L.dU_dW(W0, g), J, atol=1e-8)
+
+
+@pytest.mark.parametrize("xi,eta,nu", [(0.7, -0.4, 0.3), (math.pi / 4, 0.0, 0.25), (-2.1, 1.3, 0.45)])
+def test_modes_and_gains_match_oracle(sym, xi, eta, nu):
+    assert np.allclose(L.exact_modes(xi, eta), sym.exact_modes(xi, eta), rtol=0, atol=1e-15)
+    assert np.allclose(L.exact_gains(xi, eta, nu), sym.exact_gains(xi, eta, nu), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("method", ["TAI", "RB"])
+def test_error_measures_match_oracle(sym, method):
+    for xi, eta in ((0.6, 0.2), (-0.3, 0.5), (math.pi / 4 * math.cos(2.0), math.pi / 4 * math.sin(2.0))):
+        G = sym.G(method, 0.25, xi, eta)
+        Q, g = L.exact_modes(xi, eta), L.exact_gains(xi, eta, 0.25)
+        e = L.modal_errors(G, Q, g)
+        a, p, o = modal_errors(sym, method, 0.25, xi, eta)
+        assert np.allclose(e["amplitude"], a, rtol=1e-9, atol=1e-15)
+        assert np.allclose(e["phase"], p, rtol=1e-9, atol=1e-15)
+        assert np.allclose(e["overlap"], o, rtol=1e-12)
+        one = L.one_step_residuals(G, Q, g)
+        rep = L.repeated_step_errors(G, Q, g, 17)
+        for k in range(4):
+            assert abs(one[k] - one_step_residual(G, Q[k], g[k])) <= 1e-12 * one[k]
+            assert abs(rep[k] - repeated_step_error(G, Q[k], g[k], 17)) <= 1e-9 * rep[k]
+
+
+def test_matching_one_to_one_with_degenerate_pair():
+    rng = np.random.default_rng(5)
+    Q = rng.normal(size=(4, 16)) + 1j * rng.normal(size=(4, 16))
+    V = rng.normal(size=(16, 16)) + 1j * rng.normal(size=(16, 16))
+    V[:, 3:7] = Q.T + 1e-3 * rng.normal(size=(16, 4))
+    w = 0.4 * np.exp(1j * rng.uniform(0, 2 * np.pi, 16))
+    w[3:7] = [np.exp(0.2j), np.exp(0.2j), 0.98, 0.9 * np.exp(-0.5j)]
+    G = V @ np.diag(w) @ np.linalg.inv(V)
+    lam, ov = L.match_eigenvalues(G, Q)
+    assert np.allclose(lam, w[3:7], atol=1e-10)
+    gt, ov2, idx = match_modes(G, Q)
+    assert np.allclose(lam, gt, atol=1e-12) and len(set(idx.tolist())) == 4
+
+
+def test_polar_grid_lattice():
+    kap = math.pi / 4
+    for d in range(24):
+        th = 2 * math.pi * d / 24
+        nx, ny, mx, my = L.polar_grid(kap, th)
+        assert nx >= 4 and ny >= 4 and abs(mx) <= 1 and abs(my) <= 1
+        xi, eta = L.lattice_wavevector(nx, ny, mx, my)
+        assert abs(math.hypot(xi, eta) - kap) < 0.06 * kap
+        dth = (math.atan2(eta, xi) - th + math.pi) % (2 * math.pi) - math.pi
+        assert abs(dth) < 0.06

@@ -111,3 +111,121 @@ def test_tai_power_norm_printed(sym):
         if k % 1 == 0:
             best = max(best, float(np.linalg.norm(P, ord=2, axis=(1, 2)).max()))
     assert abs(best - 3.87) < 0.005
+
+
+# ---- Sec. 5: refinement slopes and directional modal errors -------------------------
+
+from oracle.symbol import match_modes, modal_errors, one_step_residual, repeated_step_error  # noqa: E402
+
+
+def _refine(sym, method, nu, theta, N):
+    """Errors of the four exact modes at h = kappa = c0 / (nu N): K = 1, T = 1, N steps."""
+    kap = sym.c0 / (nu * N)
+    xi, eta = kap * math.cos(theta), kap * math.sin(theta)
+    G = sym.G(method, nu, xi, eta)
+    Q, g = sym.exact_modes(xi, eta), sym.exact_gains(xi, eta, nu)
+    one = [one_step_residual(G, q, gj) for q, gj in zip(Q, g)]
+    rep = [repeated_step_error(G, q, gj, N) for q, gj in zip(Q, g)]
+    return np.array(one), np.array(rep)
+
+
+@pytest.mark.parametrize("theta_deg", [30.0, 70.0])
+def test_refinement_slopes_printed(sym, theta_deg):
+    """Sec. 5 (accuracy figure): as kappa = K h -> 0 with K and T fixed, only the acoustic
+    RB branches lose an order: their one-step and repeated-step slopes approach two,
+    every RB-TAI slope approaches three (entropy and shear RB too)."""
+    th = math.radians(theta_deg)
+    for method, want in (("TAI", (3, 3, 3, 3)), ("RB", (3, 3, 2, 2))):
+        a1, aN = _refine(sym, method, 0.25, th, 128)
+        b1, bN = _refine(sym, method, 0.25, th, 256)
+        s1, sN = np.log2(a1 / b1), np.log2(aN / bN)
+        print(method, theta_deg, "one-step slopes", np.round(s1, 3), "repeated-step slopes", np.round(sN, 3))
+        assert np.all(np.abs(s1 - np.array(want)) < 0.03), (method, s1)
+        assert np.all(np.abs(sN - np.array(want)) < 0.03), (method, sN)
+
+
+def test_exact_modes_are_pde_eigenvectors(sym):
+    """The exact modes solve the linearized Euler equations: for k = (xi, eta) / h the
+    primitive amplitudes r satisfy (u0 kx + v0 ky) r + (kx Ax + ky Ay) r = omega r with
+    omega = u0.k for entropy and shear and u0.k +- c0 |k| for the acoustic branches,
+    i.e. the gains are e^{-i omega dt}."""
+    xi, eta, nu = 0.7, -0.4, 0.3
+    Q, g = sym.exact_modes(xi, eta), sym.exact_gains(xi, eta, nu)
+    A = xi * sym.jac_x() + eta * sym.jac_y()          # h k . Jacobians, dimensionless
+    lam = nu / sym.c0
+    for q, gj in zip(Q, g):
+        r = q[4:8]                                   # the V family holds r itself
+        w = A @ r
+        om = complex(np.vdot(r, w) / np.vdot(r, r))  # omega h
+        assert np.allclose(w, om * r, atol=1e-14)
+        assert abs(np.exp(-1j * lam * om) - gj) < 1e-14
+        # the other families are the same mode sampled elsewhere in the cell
+        assert np.allclose(q[8:12], np.exp(0.5j * eta) * r) and np.allclose(q[12:16], np.exp(0.5j * xi) * r)
+
+
+def test_mode_matching_planted_eigenpairs():
+    """Eigenvector matching on a matrix with planted eigenpairs, a degenerate pair among
+    them: each exact mode gets its own planted eigenvalue, none is used twice."""
+    rng = np.random.default_rng(3)
+    Q = rng.normal(size=(4, 16)) + 1j * rng.normal(size=(4, 16))
+    V = rng.normal(size=(16, 16)) + 1j * rng.normal(size=(16, 16))
+    V[:, :4] = Q.T + 1e-3 * (rng.normal(size=(16, 4)) + 1j * rng.normal(size=(16, 4)))
+    w = 0.5 * np.exp(1j * rng.uniform(0, 2 * np.pi, 16))     # distractors inside the disk
+    w[:4] = [0.99 * np.exp(0.1j), 0.99 * np.exp(0.1j), np.exp(-0.3j), 0.97 * np.exp(0.4j)]
+    G = V @ np.diag(w) @ np.linalg.inv(V)
+    gt, ov, idx = match_modes(G, Q)
+    assert np.allclose(gt, w[:4], atol=1e-10)
+    assert len(set(idx.tolist())) == 4
+    # a degenerate pair has no preferred eigenvectors: the two modes overlap only partly
+    # with whichever basis of the pair's eigenspace comes out, the others fully
+    assert np.all(ov[2:] > 0.999) and np.all(ov[:2] > 0.3)
+
+
+def test_entropy_branch_same_for_rb_and_tai(sym):
+    """A density-only mode carries no pressure or velocity, so every node increment of it
+    vanishes and both point maps reduce to the advection map: its column of G is the
+    same for RB and RB-TAI, hence so are its modal errors."""
+    for xi, eta in ((0.5, 0.2), (-1.1, 2.0), (math.pi / 4, 0.0)):
+        q = sym.exact_modes(xi, eta)[0]
+        for nu in (0.15, 0.25):
+            d = sym.G("RB", nu, xi, eta) @ q - sym.G("TAI", nu, xi, eta) @ q
+            assert np.abs(d).max() < 1e-15
+
+
+def test_modal_errors_vanish_with_order(sym):
+    """Matched eigenvalues approach the exact gains as kappa -> 0: per step, the RB-TAI
+    amplitude error falls like kappa^4 on every branch, the RB acoustic phase error only
+    like kappa^3 (the order the repeated-step error loses), with overlaps -> 1."""
+    th = math.radians(30)
+    out = {}
+    for method in ("TAI", "RB"):
+        for kap in (0.04, 0.02):
+            out[method, kap] = modal_errors(sym, method, 0.25, kap * math.cos(th), kap * math.sin(th))
+    sA = np.log2(out["TAI", 0.04][0] / out["TAI", 0.02][0])
+    sP = np.log2(out["RB", 0.04][1] / out["RB", 0.02][1])
+    print("TAI amplitude slopes", np.round(sA, 3), "RB phase slopes", np.round(sP, 3))
+    assert np.all(np.abs(sA - 4) < 0.05)
+    assert np.all(np.abs(sP[2:] - 3) < 0.05)
+    assert np.all(out["TAI", 0.02][2] > 1 - 1e-9)
+
+
+def test_tai_acoustic_phase_below_rb_polar(sym):
+    """Sec. 5 (directional modal errors at nu = 0.25, kappa = pi/4, eight cells per
+    wavelength): RB-TAI improves on RB.  Here: over 24 directions, the largest and the
+    mean acoustic phase error of RB-TAI are below half of RB's on both acoustic branches
+    (direction by direction it is not always below: near 120 and 300 degrees, about
+    normal to the mean flow, RB's is smaller), and the entropy branch is the same."""
+    kap = math.pi / 4
+    P = {"TAI": [], "RB": []}
+    for k in range(24):
+        th = 2 * math.pi * k / 24
+        xi, eta = kap * math.cos(th), kap * math.sin(th)
+        for m in P:
+            a, p, o = modal_errors(sym, m, 0.25, xi, eta)
+            assert o.min() > 0.99
+            P[m].append(np.concatenate([a, p]))
+    T, R = np.array(P["TAI"]), np.array(P["RB"])
+    print("max acoustic phase errors TAI", T[:, 6:].max(0), "RB", R[:, 6:].max(0))
+    assert np.all(T[:, 6:].max(0) < 0.5 * R[:, 6:].max(0))
+    assert np.all(T[:, 6:].mean(0) < 0.5 * R[:, 6:].mean(0))
+    assert np.allclose(T[:, [0, 4]], R[:, [0, 4]], rtol=1e-9, atol=1e-15)
