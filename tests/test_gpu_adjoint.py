@@ -33,10 +33,12 @@ def gpu_adjoint(torch_dev, P, s0, lam, dt, scheme="tai"):
     return g.cpu().numpy()
 
 
-# tiny grids (windows wrapping onto themselves) and ragged ones (17: a node-cell covered by
-# three point blocks' windows across the periodic seam)
+# tiny grids (windows wrapping onto themselves), ragged ones (17: a node-cell covered by
+# three point blocks' windows across the periodic seam) and a grid of whole point blocks,
+# two per axis (16)
 @pytest.mark.parametrize("nx,ny,seed,scheme", [(6, 5, 1, "tai"), (7, 8, 2, "tai"), (6, 5, 3, "rb"), (7, 8, 4, "rb"),
-                                               (13, 11, 5, "tai"), (17, 12, 6, "tai"), (17, 12, 7, "rb")])
+                                               (13, 11, 5, "tai"), (17, 12, 6, "tai"), (17, 12, 7, "rb"),
+                                               (16, 16, 8, "tai"), (16, 16, 9, "rb")])
 def test_adjoint_exact_vs_oracle_jacobian(torch_dev, orc, nx, ny, seed, scheme):
     P = I.random_smooth(nx, ny, seed=seed, amp=0.15, vel=(0.35, -0.25))
     s0 = P.state()
@@ -131,11 +133,17 @@ def test_adjoint_pulse_512_dot_product(torch_dev, orc):
 def test_adjoint_repeated_calls_on_one_context(torch_dev, scheme):
     """A context's adjoint scratch (recomputed intermediates, reverse accumulators) carries
     nothing from one call to the next: consecutive calls on one context (different states
-    and cotangents, forward steps in between, a ragged 37 x 29 grid) equal calls on fresh
-    contexts, up to the order of the atomic additions."""
+    and cotangents, forward steps in between; a ragged 37 x 29 grid and a 48 x 32 one of
+    whole point blocks) equal calls on fresh contexts, up to the order of the atomic
+    additions."""
     torch, dev = torch_dev
     from paper_2605_12915_amd.stepper import Stepper
-    P = I.random_smooth(37, 29, seed=21, amp=0.15, vel=(0.3, -0.2))
+    for nx, ny in ((37, 29), (48, 32)):
+        _repeated_calls(torch, dev, Stepper, scheme, nx, ny)
+
+
+def _repeated_calls(torch, dev, Stepper, scheme, nx, ny):
+    P = I.random_smooth(nx, ny, seed=21, amp=0.15, vel=(0.3, -0.2))
     dt = P.dt_for_cfl(0.45 if scheme == "tai" else 0.19)
     rng = np.random.default_rng(22)
     st = Stepper(P.nx, P.ny, P.h, P.gamma, scheme=scheme, device=dev)
@@ -144,7 +152,7 @@ def test_adjoint_repeated_calls_on_one_context(torch_dev, scheme):
         lam = rng.normal(size=P.state().shape) * (10.0 if call % 2 else 1.0)
         s0 = x.cpu().numpy()
         got = st.adjoint(x, torch.from_numpy(lam).to(dev), dt).cpu().numpy()
-        want = gpu_adjoint(torch_dev, P, s0, lam, dt, scheme)
+        want = gpu_adjoint((torch, dev), P, s0, lam, dt, scheme)
         err = np.abs(got - want).max() / np.abs(want).max()
-        assert err < 1e-13, (call, err)
+        assert err < 1e-13, (nx, ny, call, err)
         st.step(x, dt, 2)
