@@ -33,7 +33,8 @@ typedef int32_t af_status;
 
 enum {
     AF_OK = 0,
-    AF_ERR_ARG = 1,          /* null pointer, nx < 4 or ny < 4, h <= 0, gamma <= 1, bad dt */
+    AF_ERR_ARG = 1,          /* null pointer, nx < 4 or ny < 4, nx ny > 2^31 cells, h <= 0,
+                                gamma <= 1, bad dt */
     AF_ERR_HIP = 2,          /* HIP runtime error; af_last_hip_error() returns its code */
     AF_ERR_ACOUSTIC_CFL = 3, /* some node has c_K dt / h > 1/2 (node-centred wedges invalid) */
     AF_ERR_FOOT = 4,         /* some convective foot moved one cell or more */
@@ -51,7 +52,7 @@ enum {
 };
 
 typedef struct af_config {
-    int32_t nx, ny;      /* cells in x and y (>= 4) */
+    int32_t nx, ny;      /* cells in x and y (>= 4; nx ny <= 2^31) */
     double x0, y0;       /* lower-left corner (informational) */
     double h;            /* cell size, dx = dy = h (Sec. 2) */
     double gamma;        /* ratio of specific heats (> 1) */
@@ -150,8 +151,8 @@ af_status af_time_steps(af_ctx* ctx, const af_state* s, double dt, int32_t nstep
  * per grid.  hip_stream is borrowed; replays run on an internal stream ordered after
  * it. */
 af_status af_init_batch(const af_config* cfgs, int32_t n, void* hip_stream, af_ctx** out);
-/* (af_init_batch errors: AF_ERR_ARG for n outside 1..4096 or a config af_init would
- * reject; AF_ERR_UNSUPPORTED for a config that is not AF_F32, or whose AF_SCHEME_RB
+/* (af_init_batch errors: AF_ERR_ARG for n outside 1..4096, a config af_init would
+ * reject, or more than 2^31 cells in all; AF_ERR_UNSUPPORTED for a config that is not AF_F32, or whose AF_SCHEME_RB
  * flag differs from the first config's.  Configs are checked before any HIP call.) */
 
 /* Advance every grid q of a batch context by nsteps (1..65536) steps of size dts[q]

@@ -293,12 +293,18 @@ const char* af_status_string(af_status s) {
 
 int32_t af_last_hip_error(void) { return g_last_hip; }
 
+// Largest grid a context accepts: 2^31 cells (275 GB of FP64 state, more than one GPU
+// holds with a second state), which keeps every byte count in size_t and every launch
+// within HIP's 2^32 work-items per grid dimension.
+constexpr uint64_t kMaxCells = uint64_t(1) << 31;
+
 af_status af_init(const af_config* cfg, void* hip_stream, af_ctx** out) {
     if (!cfg || !out) return AF_ERR_ARG;
     *out = nullptr;
     if (cfg->nx < 4 || cfg->ny < 4 || !(cfg->h > 0.0) || !(cfg->gamma > 1.0) || !std::isfinite(cfg->h) ||
         !std::isfinite(cfg->gamma))
         return AF_ERR_ARG;
+    if ((uint64_t)cfg->nx * (uint64_t)cfg->ny > kMaxCells) return AF_ERR_ARG;
     if (cfg->precision != AF_F64 && cfg->precision != AF_F32) return AF_ERR_ARG;
     if (cfg->precision == AF_F32 && (!(cfg->bg[0] > 0.0) || !(cfg->bg[3] > 0.0))) return AF_ERR_ARG;
     af_ctx* c = new (std::nothrow) af_ctx();
@@ -517,9 +523,14 @@ af_status af_time_steps(af_ctx* c, const af_state* s, double dt, int32_t nsteps,
 af_status af_init_batch(const af_config* cfgs, int32_t n, void* hip_stream, af_ctx** out) {
     if (!cfgs || !out || n < 1 || n > 4096) return AF_ERR_ARG;
     *out = nullptr;
+    uint64_t total = 0;
     for (int q = 0; q < n; ++q) {
         const af_config& cf = cfgs[q];
-        if (cf.nx < 4 || cf.ny < 4 || !(cf.h > 0.0) || !(cf.gamma > 1.0) || !std::isfinite(cf.h)) return AF_ERR_ARG;
+        if (cf.nx < 4 || cf.ny < 4 || !(cf.h > 0.0) || !(cf.gamma > 1.0) || !std::isfinite(cf.h) ||
+            !std::isfinite(cf.gamma))
+            return AF_ERR_ARG;
+        total += (uint64_t)cf.nx * (uint64_t)cf.ny;
+        if (total > kMaxCells) return AF_ERR_ARG;
         if (cf.precision != AF_F32) return AF_ERR_UNSUPPORTED;
         if (!(cf.bg[0] > 0.0) || !(cf.bg[3] > 0.0)) return AF_ERR_ARG;
         if ((cf.flags & AF_SCHEME_RB) != (cfgs[0].flags & AF_SCHEME_RB)) return AF_ERR_UNSUPPORTED;   // one scheme per batch

@@ -44,6 +44,11 @@ def test_bad_config_rejected_on_host(L):
     cfg.h, cfg.gamma = 0.1, 1.0
     assert L.af_init(ctypes.byref(cfg), None, ctypes.byref(ctx)) == _lib.AF_ERR_ARG
     assert L.af_init(None, None, ctypes.byref(ctx)) == _lib.AF_ERR_ARG
+    # beyond 2^31 cells (byte counts and launch sizes would overflow)
+    cfg.gamma, cfg.nx, cfg.ny = 1.4, 65536, 32769
+    assert L.af_init(ctypes.byref(cfg), None, ctypes.byref(ctx)) == _lib.AF_ERR_ARG
+    cfg.nx, cfg.ny = 2 ** 31 - 1, 2 ** 31 - 1
+    assert L.af_init(ctypes.byref(cfg), None, ctypes.byref(ctx)) == _lib.AF_ERR_ARG
     assert L.af_step(None, None, 0.1, 1) == _lib.AF_ERR_ARG
     assert L.af_diagnostics(None, None, 0.1, None) == _lib.AF_ERR_ARG
 
@@ -73,6 +78,9 @@ def test_bad_batch_config_rejected_on_host(L):
     cfgs[1].ny = 3
     assert L.af_init_batch(cfgs, 2, None, ctypes.byref(ctx)) == _lib.AF_ERR_ARG
     cfgs[1].ny, cfgs[1].bg[0] = 8, 0.0
+    assert L.af_init_batch(cfgs, 2, None, ctypes.byref(ctx)) == _lib.AF_ERR_ARG
+    cfgs[1].bg[0] = 1.0
+    cfgs[0].nx = cfgs[0].ny = cfgs[1].nx = cfgs[1].ny = 40000    # 3.2e9 cells in all
     assert L.af_init_batch(cfgs, 2, None, ctypes.byref(ctx)) == _lib.AF_ERR_ARG
     assert L.af_step_batch(None, None, None, 1) == _lib.AF_ERR_ARG
     assert L.af_batch_info(None, None, 0) == -1
