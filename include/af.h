@@ -115,9 +115,13 @@ af_status af_read_status(af_ctx* ctx, af_status* status);
 
 /* Reverse-mode derivative of one step (AF_F64 only; either point update, TAI or
  * AF_SCHEME_RB): cot_n = (d step / d state_n)^T cot_np1 at fixed dt, where step is the
- * map of af_step_out.  primal_n: the state the
- * step was taken from; cot_np1: cotangent of the step's output; cot_n: overwritten
- * (not accumulated).  All three are caller-owned device states of doubles. */
+ * map of af_step_out.  primal_n: the state the step was taken from; cot_np1:
+ * cotangent of the step's output; cot_n: overwritten (not accumulated), distinct from
+ * the other two.  All three are caller-owned device states of doubles.  Asynchronous
+ * on the context stream; the first call allocates the context's adjoint scratch (56
+ * planes).  Errors: AF_ERR_ARG for a bad pointer or dt (<= 0 or not finite),
+ * AF_ERR_UNSUPPORTED on an AF_F32 or batch context.  The derivative of the foot's cell
+ * (a floor) is taken as zero. */
 af_status af_step_adjoint(af_ctx* ctx, const af_state* primal_n, const af_state* cot_np1,
                           af_state* cot_n, double dt);
 

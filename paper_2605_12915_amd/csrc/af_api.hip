@@ -426,7 +426,8 @@ af_status af_read_status(af_ctx* c, af_status* status) {
 
 af_status af_step_adjoint(af_ctx* c, const af_state* primal_n, const af_state* cot_np1, af_state* cot_n,
                           double dt) {
-    if (!c || !state_ok(primal_n) || !state_ok(cot_np1) || !state_ok(cot_n) || !(dt > 0.0)) return AF_ERR_ARG;
+    if (!c || !state_ok(primal_n) || !state_ok(cot_np1) || !state_ok(cot_n) || !(dt > 0.0) || !std::isfinite(dt))
+        return AF_ERR_ARG;
     if (c->f32 || c->nbatch) return AF_ERR_UNSUPPORTED;
     if (!c->adj_scratch) AF_HIP(hipMalloc(&c->adj_scratch, af::scratch_bytes_adjoint_f64(c->cfg.nx, c->cfg.ny)));
     af::StepArgs a;
