@@ -106,7 +106,8 @@ af_status af_init(const af_config* cfg, void* hip_stream, af_ctx** out);
 af_status af_step(af_ctx* ctx, af_state* inout, double dt, int32_t nsteps);
 
 /* One step from `in` to `out` (distinct buffers, both caller-owned); same operation
- * and errors as af_step with nsteps = 1, except that `in` is never modified. */
+ * and errors as af_step with nsteps = 1, except that `in` is never modified.
+ * AF_ERR_ARG if the two states share a plane pointer. */
 af_status af_step_out(af_ctx* ctx, const af_state* in, af_state* out, double dt);
 
 /* Read and clear the device status flag accumulated since the last read
@@ -119,7 +120,8 @@ af_status af_read_status(af_ctx* ctx, af_status* status);
  * cotangent of the step's output; cot_n: overwritten (not accumulated), distinct from
  * the other two.  All three are caller-owned device states of doubles.  Asynchronous
  * on the context stream; the first call allocates the context's adjoint scratch (56
- * planes).  Errors: AF_ERR_ARG for a bad pointer or dt (<= 0 or not finite),
+ * planes).  Errors: AF_ERR_ARG for a bad pointer or dt (<= 0 or not finite) or for
+ * cot_n sharing a plane pointer with cot_np1 or primal_n,
  * AF_ERR_UNSUPPORTED on an AF_F32 or batch context.  The derivative of the foot's cell
  * (a floor) is taken as zero. */
 af_status af_step_adjoint(af_ctx* ctx, const af_state* primal_n, const af_state* cot_np1,

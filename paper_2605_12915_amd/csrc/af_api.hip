@@ -92,6 +92,17 @@ bool state_ok(const af_state* s) {
     return true;
 }
 
+// true if the two states have a plane pointer in common (an output that must not alias)
+bool share_plane(const af_state* a, const af_state* b) {
+    void *pa[16], *pb[16];
+    planes_of(a, pa);
+    planes_of(b, pb);
+    for (int k = 0; k < 16; ++k)
+        for (int q = 0; q < 16; ++q)
+            if (pa[k] == pb[q]) return true;
+    return false;
+}
+
 af_status status_from_bits(unsigned b) {
     if (b & af::SB_NONPHYS) return AF_ERR_NONPHYSICAL;
     if (b & af::SB_CFL) return AF_ERR_ACOUSTIC_CFL;
@@ -373,6 +384,7 @@ void af_destroy(af_ctx* c) {
 
 af_status af_step_out(af_ctx* c, const af_state* in, af_state* out, double dt) {
     if (!c || !state_ok(in) || !state_ok(out) || !(dt > 0.0) || !std::isfinite(dt)) return AF_ERR_ARG;
+    if (share_plane(in, out)) return AF_ERR_ARG;
     if (c->nbatch) return AF_ERR_UNSUPPORTED;
     void *pi[16], *po[16];
     planes_of(in, pi);
@@ -428,6 +440,7 @@ af_status af_step_adjoint(af_ctx* c, const af_state* primal_n, const af_state* c
                           double dt) {
     if (!c || !state_ok(primal_n) || !state_ok(cot_np1) || !state_ok(cot_n) || !(dt > 0.0) || !std::isfinite(dt))
         return AF_ERR_ARG;
+    if (share_plane(cot_n, cot_np1) || share_plane(cot_n, primal_n)) return AF_ERR_ARG;
     if (c->f32 || c->nbatch) return AF_ERR_UNSUPPORTED;
     if (!c->adj_scratch) AF_HIP(hipMalloc(&c->adj_scratch, af::scratch_bytes_adjoint_f64(c->cfg.nx, c->cfg.ny)));
     af::StepArgs a;

@@ -82,6 +82,19 @@ def test_step_out_leaves_input(torch_dev, orc):
     torch.cuda.synchronize()
     assert np.array_equal(x.cpu().numpy(), s0)
     assert _err(y.cpu().numpy(), orc.step(s0, P.h, P.gamma, dt)).max() <= TOL
+    # an output that aliases an input is refused before anything runs
+    from paper_2605_12915_amd._lib import AF_ERR_ARG, AfError
+    with pytest.raises(AfError) as e:
+        st.step_out(x, dt, x)
+    assert e.value.code == AF_ERR_ARG
+    lam = torch.ones_like(x)
+    with pytest.raises(AfError) as e:
+        st.adjoint(x, lam, dt, out=lam)
+    assert e.value.code == AF_ERR_ARG
+    with pytest.raises(AfError) as e:
+        st.adjoint(x, lam, dt, out=x)
+    assert e.value.code == AF_ERR_ARG
+    assert np.array_equal(x.cpu().numpy(), s0)
 
 
 def test_free_stream(torch_dev):
