@@ -204,3 +204,24 @@ def test_gpu_refinement_slopes(torch_dev):
                   "repeated-step slopes", np.round(sN, 3))
             assert np.all(np.abs(s1 - np.array(want)) < 0.1), (method, mx, my, s1)
             assert np.all(np.abs(sN - np.array(want)) < 0.1), (method, mx, my, sN)
+
+
+def test_gpu_stability_limits(torch_dev):
+    """Sec. 5.2 from the GPU step's measured G: RB-TAI stays stable at nu = 0.5 over a
+    12 x 12 lattice of wave vectors (spectral radius 1 to round-off), while RB is unstable
+    at nu = 0.25 and stable at 0.19 along the diagonal near the printed critical
+    direction (44.4 degrees), |k h| = 0.56."""
+    from paper_2605_12915_amd.linear import SymbolMeter
+    dev = torch_dev[1]
+    m = SymbolMeter(12, 12, "tai", device=dev)
+    worst = 0.0
+    for mx in range(0, 7):
+        for my in range(-5, 7):
+            worst = max(worst, float(np.abs(np.linalg.eigvals(m.measure(mx, my, 0.5))).max()))
+    print("TAI nu = 0.5: max spectral radius over the lattice - 1 =", worst - 1.0)
+    assert worst <= 1.0 + 1e-9
+    rb = SymbolMeter(16, 16, "rb", device=dev)
+    g25 = float(np.abs(np.linalg.eigvals(rb.measure(1, 1, 0.25))).max())
+    g19 = float(np.abs(np.linalg.eigvals(rb.measure(1, 1, 0.19))).max())
+    print("RB at 45 degrees, |k h| = 0.56: spectral radius - 1 =", g25 - 1.0, "(nu 0.25),", g19 - 1.0, "(nu 0.19)")
+    assert g25 > 1.0 + 1e-6 and g19 < 1.0
