@@ -303,7 +303,7 @@ def form_batch(torch, dev, count, steps, big_fp32_rate):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "single-GPU benchmark: the step has no multi-GPU path; --gpus must be 1"}))
         sys.exit(2)
     import numpy as np
     import torch
