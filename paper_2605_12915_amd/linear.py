@@ -2,7 +2,7 @@
 
 About a uniform state W0 the step is, to first order, a 16x16 amplification matrix
 G(xi, eta) acting on a Fourier mode's amplitudes over the four families (cell average,
-V, Ev, Eh; every family as primitive perturbations).  `measure_symbol` obtains it
+V, Ev, Eh; every family as primitive perturbations).  `SymbolMeter.measure` obtains it
 from the library's FP64 step itself: for each of the 16 amplitudes, one periodic mode
 e^{i(xi i + eta j)} on an nx x ny grid with xi = 2 pi mx / nx, eta = 2 pi my / ny, four
 steps (real and imaginary part, +-eps) and central differences; the response of every
@@ -18,7 +18,9 @@ On G, the accuracy measures of Sec. 5:
     fixed K and T as kappa = K h -> 0;
   * the directional modal amplitude and phase errors (eq. modal-amplitude-phase-errors)
     of the numerical eigenvalues matched one-to-one to the q_j by largest normalized
-    right-eigenvector overlap.
+    right-eigenvector overlap;
+  * the one-step pressure gain of the acoustic mode at the Ev nodes and its error
+    (Sec. 5.3).
 
 Only the step runs on the GPU; the differences, projections and eigen-decompositions are
 host post-processing of its outputs (numpy).
@@ -26,7 +28,7 @@ host post-processing of its outputs (numpy).
 from __future__ import annotations
 
 import math
-from typing import Dict, List, Optional, Sequence, Tuple
+from typing import Dict, List, Sequence, Tuple
 
 import numpy as np
 
@@ -185,6 +187,16 @@ def modal_errors(G: np.ndarray, Q: np.ndarray, g: np.ndarray) -> Dict[str, np.nd
     lam, ov = match_eigenvalues(G, Q)
     return {"amplitude": np.abs(np.abs(lam) - 1.0), "phase": np.abs(np.angle(lam / g)), "overlap": ov,
             "eigenvalue": lam}
+
+
+def pressure_gain(G: np.ndarray, xi: float, eta: float, nu: float, W0: Sequence[float] = PAPER_BACKGROUND,
+                  gamma: float = 1.4) -> Tuple[complex, float]:
+    """Sec. 5.3: one-step gain of the Ev-node pressure for the exact acoustic mode
+    (branch +), and its distance from the exact gain."""
+    q = exact_modes(xi, eta, W0, gamma)[2]
+    k = 8 + 3                                       # Ev family, pressure
+    g = complex((G @ q)[k] / q[k])
+    return g, abs(g - exact_gains(xi, eta, nu, W0, gamma)[2])
 
 
 def polar_grid(kappa: float, theta: float, nmax: int = 512) -> Tuple[int, int, int, int]:

@@ -126,9 +126,17 @@ def test_gpu_pressure_gain_near_printed(torch_dev):
     st = Stepper(N, N, h, GAMMA, device=dev)
     printed = {0.2: 8.48e-3, 0.3: 8.75e-3, 0.4: 7.02e-3, 0.5: 5.15e-3}
     lattice = [(7, 0), (0, 7), (-7, 0), (0, -7), (5, 5), (-5, 5), (-5, -5), (5, -5)]
+    from paper_2605_12915_amd.linear import SymbolMeter, pressure_gain
+    meter = SymbolMeter(N, N, "tai", device=dev)
     for nu, pmax in printed.items():
         dt = nu * h / sym.c0
         errs = []
+        for mx, my in lattice[:2]:
+            # the library's own measure on the measured G agrees
+            xi, eta = 2 * math.pi * mx / N, 2 * math.pi * my / N
+            g, e = pressure_gain(meter.measure(mx, my, nu), xi, eta, nu)
+            assert abs(g - sym.pressure_gain("TAI", math.hypot(xi, eta), math.atan2(eta, xi), nu)) < 1e-9
+            assert abs(e - abs(g - sym.exact_gain(xi, eta, nu))) < 1e-15
         for mx, my in lattice:
             xi, eta = 2 * math.pi * mx / N, 2 * math.pi * my / N
             q = sym.acoustic_mode(xi, eta, +1)

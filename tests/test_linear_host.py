@@ -74,3 +74,13 @@ def test_polar_grid_lattice():
         assert abs(math.hypot(xi, eta) - kap) < 0.06 * kap
         dth = (math.atan2(eta, xi) - th + math.pi) % (2 * math.pi) - math.pi
         assert abs(dth) < 0.06
+
+
+def test_pressure_gain_matches_oracle(sym):
+    for nu in (0.2, 0.5):
+        for th in (0.0, 0.7, 2.0):
+            xi, eta = math.cos(th), math.sin(th)
+            G = sym.G("TAI", nu, xi, eta)
+            g, err = L.pressure_gain(G, xi, eta, nu)
+            assert abs(g - sym.pressure_gain("TAI", 1.0, th, nu)) < 1e-13
+            assert abs(err - abs(g - sym.exact_gain(xi, eta, nu))) < 1e-15
