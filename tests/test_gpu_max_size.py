@@ -1,0 +1,100 @@
+"""The FP64 step and its adjoint on a 6400 x 6400 grid (41 M cells): the adjoint's 56
+scratch planes then span 2.3e9 elements, past 32-bit offsets, and the state is 5.2 GB.
+The oracle cannot step a grid this size in a test, so the checks are properties that
+hold exactly at any size:
+  * free stream: a uniform state is preserved to round-off (Sec. 4, exact free-stream
+    preservation);
+  * conservation: the four totals of the averages are unchanged up to summation
+    round-off (the flux differences telescope on a periodic grid, eq. af-average-update);
+  * the adjoint of conservation: since sum_cells Ubar_k^{n+1} = sum_cells Ubar_k^n for
+    every state, the cotangent that is one on average plane k and zero elsewhere is
+    mapped to itself (the flux cotangents are differences of equal values: zero).
+The state is built on the GPU with torch (test set-up only): the Fourier-mode flow of
+the throughput benchmark (rho = 1, p = 1/1.4, (u, v) = (0.5, 0.3), four modes of 1e-3),
+point values sampled at the nodes and averages taken as U of the cell-centre value
+(exact averages are not needed for these properties)."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+N = 6400
+GAMMA = 1.4
+
+
+@pytest.fixture(scope="module")
+def big():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_12915_amd.stepper import Stepper
+    dev = torch.device("cuda:0")
+    print("building the", N, "x", N, "state on the GPU", flush=True)
+    h = 1.0 / N
+    c = torch.arange(N, dtype=torch.float64, device=dev) * h
+    modes = ((1, 2, 0.3), (-3, 1, 1.1), (2, -5, 2.0), (7, 4, 4.2))
+
+    def prim(ox, oy):
+        X = (c + ox * h)[None, :]
+        Y = (c + oy * h)[:, None]
+        d = torch.zeros((N, N), dtype=torch.float64, device=dev)
+        for kx, ky, ph in modes:
+            d += 1e-3 * torch.cos(2 * math.pi * (kx * X + ky * Y) + ph)
+        return 1.0 + d, 0.5 + d, 0.3 - d, 1.0 / GAMMA + d
+
+    s = torch.empty((16, N, N), dtype=torch.float64, device=dev)
+    r, u, v, p = prim(0.5, 0.5)
+    s[0], s[1], s[2] = r, r * u, r * v
+    s[3] = p / (GAMMA - 1) + 0.5 * r * (u * u + v * v)
+    for base, (ox, oy) in ((4, (0.0, 0.0)), (8, (0.0, 0.5)), (12, (0.5, 0.0))):
+        for k, f in enumerate(prim(ox, oy)):
+            s[base + k] = f
+    del r, u, v, p
+    st = Stepper(N, N, h, GAMMA, check_errors=True, device=dev)
+    dt = 0.4 * h / 1.6            # CFL 0.4 with max(|u| + c) ~ 0.58 + 1.0
+    return torch, dev, st, s, dt
+
+
+def test_max_size_conservation(big):
+    torch, dev, st, s, dt = big
+    y = st.step_out(s, dt)
+    assert st.read_status() == 0
+    for k in range(4):
+        a, b = float(s[k].sum()), float(y[k].sum())
+        scale = float(s[k].abs().sum())
+        print("plane", k, "total change / sum |U|:", abs(b - a) / scale)
+        assert abs(b - a) <= 1e-13 * scale
+    assert bool(torch.isfinite(y).all())
+    # the point values moved (the step did something) and stay near the data
+    assert float((y[4] - s[4]).abs().max()) > 1e-6
+    assert float((y[4] - s[4]).abs().max()) < 1e-2
+    del y
+
+
+def test_max_size_adjoint_of_conservation(big):
+    torch, dev, st, s, dt = big
+    for k in range(4):
+        e = torch.zeros_like(s)
+        e[k] = 1.0
+        g = st.adjoint(s, e, dt)
+        err = float((g - e).abs().max())
+        print("adjoint of total", k, ": max |cot_n - e_k| =", err)
+        assert err <= 1e-13
+        del g, e
+
+
+def test_max_size_free_stream(big):
+    torch, dev, st, s, dt = big
+    W = (1.3, 0.7, -0.4, 0.9)
+    U = (W[0], W[0] * W[1], W[0] * W[2], W[3] / (GAMMA - 1) + 0.5 * W[0] * (W[1] ** 2 + W[2] ** 2))
+    vals = list(U) + list(W) * 3
+    x = torch.empty_like(s)
+    for k in range(16):
+        x[k].fill_(vals[k])
+    y = st.step_out(x, 0.4 * (1.0 / N) / 2.5, torch.empty_like(s))
+    assert st.read_status() == 0
+    for k in range(16):
+        dev_k = float((y[k] - vals[k]).abs().max())
+        assert dev_k <= 1e-14 * max(1.0, abs(vals[k])), (k, dev_k)
