@@ -1,5 +1,6 @@
 """Drivers for the paper's numerical experiments on the GPU step (Sec. 4.2 mixed
-wave packet; Sec. 6 acoustic pulse, low-Mach shear, Kelvin-Helmholtz robustness).
+wave packet; Sec. 6 isentropic vortex convergence and CFL sweep, acoustic pulse,
+low-Mach shear, Kelvin-Helmholtz robustness).
 
 Every driver steps a seeded analytic initial condition (inputs.py) with the HIP
 step through the C ABI and reads the FP64 diagnostics (af_diagnostics) along the
@@ -101,3 +102,45 @@ def kelvin_helmholtz(n: int = 64, t_end: float = 15.0, cfl: float = 0.475, **kw)
     r["min_rho"] = min(d["min_rho"] for _, d in H)
     r["min_p"] = min(d["min_p"] for _, d in H)
     return r
+
+
+def paper_vortex(n: int) -> I.Problem:
+    """Sec. 6, isentropic vortex: [0, 10] x [-5, 5], centre (5, 0), beta = 5, carried by
+    (u, v) = (1, 0); after t = 10 (one period) the exact solution is the initial data."""
+    return I.isentropic_vortex(n, center=(5.0, 0.0), uinf=(1.0, 0.0), y0=-5.0)
+
+
+def vortex_error(n: int, cfl: float, scheme: str = "tai", t_end: float = 10.0, **kw) -> dict:
+    """One period of the vortex at the given CFL: L2 (sqrt(h^2 sum e^2)) and L-inf errors
+    of the density averages against the exact ones.  An unstable run (a non-physical
+    state or a foot or acoustic-CFL violation raised by the step's checks) is reported
+    with stable = False instead of errors."""
+    from ._lib import AfError
+    P = paper_vortex(n)
+    exact = P.state()[0]
+    try:
+        r = run(P, t_end, cfl, scheme=scheme, every=50, **kw)
+    except AfError as e:
+        return {"n": n, "cfl": cfl, "scheme": scheme, "stable": False, "error": str(e)}
+    e = r["state"][0].cpu().numpy() - exact
+    if not np.isfinite(e).all():
+        return {"n": n, "cfl": cfl, "scheme": scheme, "stable": False, "error": "non-finite state"}
+    return {"n": n, "cfl": cfl, "scheme": scheme, "stable": True, "steps": r["steps"],
+            "l2": float(math.sqrt(P.h * P.h * float(np.sum(e * e)))), "linf": float(np.abs(e).max())}
+
+
+def vortex_convergence(ns=(16, 32, 64, 128), cfl: float = 0.3, scheme: str = "tai", **kw) -> dict:
+    """Sec. 6 grid-refinement study of the vortex at CFL 0.3: errors per grid and the
+    observed orders between consecutive grids."""
+    rows = [vortex_error(n, cfl, scheme, **kw) for n in ns]
+    orders = []
+    for a, b in zip(rows, rows[1:]):
+        orders.append({"l2": math.log(a["l2"] / b["l2"]) / math.log(b["n"] / a["n"]),
+                       "linf": math.log(a["linf"] / b["linf"]) / math.log(b["n"] / a["n"])})
+    return {"rows": rows, "orders": orders}
+
+
+def vortex_cfl_sweep(n: int = 64, cfls=(0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0),
+                     scheme: str = "tai", **kw) -> list:
+    """Sec. 6 CFL sweep of the vortex on one grid: error (or instability) per CFL."""
+    return [vortex_error(n, c, scheme, **kw) for c in cfls]

@@ -98,3 +98,42 @@ def test_kelvin_helmholtz_robustness(torch_dev, scheme, cfl):
     print("Kelvin-Helmholtz", scheme, r["steps"], "steps, min rho", r["min_rho"], "min p", r["min_p"])
     assert r["t"] == 15.0
     assert r["min_rho"] > 0.0 and r["min_p"] > 0.0
+
+
+def test_vortex_convergence(torch_dev):
+    """Sec. 6 isentropic vortex, one period at CFL 0.3: RB-TAI follows a third-order
+    trend in the L2 error of the density averages over 16^2-128^2 and is more accurate
+    than RB on every grid."""
+    from paper_2605_12915_amd import experiments as E
+    ns = (16, 32, 64, 128)
+    tai = E.vortex_convergence(ns, 0.3, "tai", device=torch_dev[1])
+    rb = E.vortex_convergence(ns, 0.3, "rb", device=torch_dev[1])
+    o = [x["l2"] for x in tai["orders"]]
+    print("vortex L2 errors TAI", [r["l2"] for r in tai["rows"]], "RB", [r["l2"] for r in rb["rows"]],
+          "TAI orders", o)
+    assert np.mean(o) > 2.8 and min(o[1:]) > 2.9
+    for a, b in zip(tai["rows"], rb["rows"]):
+        assert a["l2"] < b["l2"] and a["linf"] < b["linf"]
+
+
+def test_vortex_cfl_range(torch_dev):
+    """Sec. 6 CFL sweep of the vortex: RB-TAI stays stable up to CFL 1 (acoustic CFL
+    0.39) while RB fails above ~0.4; RB-TAI's error is U-shaped in the CFL number, its
+    minimum moving to a lower CFL on the finer grid, and below RB's wherever RB runs."""
+    from paper_2605_12915_amd import experiments as E
+    cfls = (0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0)
+    best = {}
+    for n in (32, 64):
+        tai = E.vortex_cfl_sweep(n, cfls, "tai", device=torch_dev[1])
+        rb = E.vortex_cfl_sweep(n, cfls, "rb", device=torch_dev[1])
+        print(n, "TAI", [(r["cfl"], r.get("l2")) for r in tai], "RB", [(r["cfl"], r.get("l2")) for r in rb])
+        assert all(r["stable"] for r in tai)
+        assert rb[3]["stable"] and not rb[4]["stable"] and not rb[-1]["stable"]
+        e = np.array([r["l2"] for r in tai])
+        k = int(np.argmin(e))
+        assert 0 < k < len(cfls) - 1 and e[0] > 1.3 * e[k] and e[-1] > 1.3 * e[k]
+        best[n] = cfls[k]
+        for a, b in zip(tai, rb):
+            if b["stable"]:
+                assert a["l2"] < b["l2"]
+    assert best[64] < best[32]
