@@ -137,3 +137,17 @@ def test_vortex_cfl_range(torch_dev):
             if b["stable"]:
                 assert a["l2"] < b["l2"]
     assert best[64] < best[32]
+
+
+def test_pulse_refinement(torch_dev):
+    """Sec. 6 acoustic pulse, t = 2.5, CFL 0.475: the largest radial asymmetry of the
+    point pressures and the largest vertex-pressure error against a 1280^2 solution both
+    fall under refinement (dx = 0.05, 0.025, 0.0125) with orders approaching three."""
+    from paper_2605_12915_amd import experiments as E
+    r = E.pulse_refinement((160, 320, 640), 1280, device=torch_dev[1])
+    print("pulse refinement:", r["rows"], r["orders"], "reference asymmetry", r["reference_asymmetry"])
+    a = [x["asymmetry"] for x in r["rows"]] + [r["reference_asymmetry"]]
+    e = [x["max_error"] for x in r["rows"]]
+    assert all(u > v for u, v in zip(a, a[1:])) and all(u > v for u, v in zip(e, e[1:]))
+    assert r["orders"][-1]["max_error"] > 2.5
+    assert r["orders"][-1]["asymmetry"] > 2.2 and np.log2(a[-2] / a[-1]) > 2.4
