@@ -79,6 +79,10 @@ def test_low_mach_shear_vorticity_integrals(torch_dev, orc):
           "entropy", H[0][1]["entropy"], "->", H[-1][1]["entropy"])
     assert r["t"] == 80.0
     assert r["max_abs_vorticity_integral"] < 1e-15
+    # entropy functional: non-increasing at every sample and nearly unchanged (Sec. 6)
+    e = [d["entropy"] for _, d in H]
+    assert all(b <= a + 1e-15 * abs(a) for a, b in zip(e, e[1:]))
+    assert 0.0 <= (e[0] - e[-1]) / abs(e[0]) < 1e-5
     assert r["max_mass_drift"] < 1e-14
     assert 0.2 < r["enstrophy_ratio_final"] < 1.0
     P = I.low_mach_shear(64)
@@ -92,12 +96,18 @@ def test_low_mach_shear_vorticity_integrals(torch_dev, orc):
 @pytest.mark.parametrize("scheme,cfl", [("tai", 0.475), ("rb", 0.25)])
 def test_kelvin_helmholtz_robustness(torch_dev, scheme, cfl):
     """Sec. 6 robustness test, 64^2 to t = 15 at the paper's CFL numbers, no limiter:
-    every step passes the non-physical, foot and acoustic-CFL checks."""
+    every step passes the non-physical, foot and acoustic-CFL checks; the entropy
+    functional never increases and falls far more than in the smooth low-Mach shear
+    (the paper's contrast between the two shear tests)."""
     from paper_2605_12915_amd import experiments as E
     r = E.kelvin_helmholtz(64, 15.0, cfl, scheme=scheme, device=torch_dev[1])
-    print("Kelvin-Helmholtz", scheme, r["steps"], "steps, min rho", r["min_rho"], "min p", r["min_p"])
+    e = [d["entropy"] for _, d in r["history"]]
+    print("Kelvin-Helmholtz", scheme, r["steps"], "steps, min rho", r["min_rho"], "min p", r["min_p"],
+          "entropy", e[0], "->", e[-1])
     assert r["t"] == 15.0
     assert r["min_rho"] > 0.0 and r["min_p"] > 0.0
+    assert all(b <= a + 1e-15 * abs(a) for a, b in zip(e, e[1:]))
+    assert (e[0] - e[-1]) / abs(e[0]) > 1e-2
 
 
 def test_vortex_convergence(torch_dev):
