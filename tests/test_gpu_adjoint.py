@@ -113,6 +113,33 @@ def test_rollout_gradient_vs_fd(torch_dev):
         assert rel < 1e-6
 
 
+@pytest.mark.parametrize("scheme", ["tai", "rb"])
+def test_rollout_gradient_vs_oracle_jvp(torch_dev, orc, scheme):
+    """The checkpointed rollout's gradient (autograd through 30 steps, checkpoints every
+    7, so the last segment is short) against the oracle's own derivative: the
+    complex-step JVP chained through the same 30 steps gives <w, J_30 v>, which must
+    equal <grad of <w, state_30>, v> for random w and v (all 16 planes)."""
+    torch, dev = torch_dev
+    from paper_2605_12915_amd.autodiff import rollout
+    from paper_2605_12915_amd.stepper import Stepper
+    P = I.random_smooth(24, 20, seed=31, amp=0.1, vel=(0.3, 0.2))
+    s0 = P.state()
+    dt = P.dt_for_cfl(0.45 if scheme == "tai" else 0.19)
+    st = Stepper(P.nx, P.ny, P.h, P.gamma, scheme=scheme, device=dev)
+    rng = np.random.default_rng(32)
+    w = rng.normal(size=s0.shape)
+    v = rng.normal(size=s0.shape)
+    x = torch.from_numpy(s0).to(dev).requires_grad_(True)
+    torch.sum(torch.from_numpy(w).to(dev) * rollout(x, st, dt, 30, 7)).backward()
+    lhs = float(np.sum(x.grad.cpu().numpy() * v))
+    sc, tc = s0, v
+    for _ in range(30):
+        sc, tc = orc.step_jvp(sc, tc, P.h, P.gamma, dt, scheme=0 if scheme == "tai" else 1)
+    rhs = float(np.sum(w * tc))
+    print(scheme, "rollout <grad, v>", lhs, "oracle <w, J v>", rhs)
+    assert abs(lhs - rhs) <= 1e-11 * np.sqrt(np.sum(w * w) * np.sum(tc * tc))
+
+
 def test_adjoint_pulse_512_dot_product(torch_dev, orc):
     """512^2 acoustic pulse of the gradient benchmark: <lambda, J v> from the oracle's
     complex-step JVP equals <J^T lambda, v> from the GPU adjoint."""
