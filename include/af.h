@@ -18,7 +18,10 @@
  *
  * Every function returns an af_status; none aborts or prints.  Work is enqueued on
  * the HIP stream given to af_init (borrowed, not owned) and is asynchronous unless
- * stated otherwise.
+ * stated otherwise.  A context is not thread-safe: its calls must not overlap (they
+ * share its scratch, status flag and events); distinct contexts are independent.
+ * The caller keeps the state buffers alive and unmodified until the enqueued work
+ * that uses them has completed on the stream.
  */
 #ifndef AF_H_
 #define AF_H_
