@@ -214,3 +214,43 @@ def vortex_cfl_sweep(n: int = 64, cfls=(0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 
                      scheme: str = "tai", **kw) -> list:
     """Sec. 6 CFL sweep of the vortex on one grid: error (or instability) per CFL."""
     return [vortex_error(n, c, scheme, **kw) for c in cfls]
+
+
+def _main(argv=None) -> int:
+    """python -m paper_2605_12915_amd.experiments NAME [--scheme tai|rb]: run one
+    experiment with its default settings and print its results as one JSON line."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(prog="python -m paper_2605_12915_amd.experiments")
+    ap.add_argument("name", choices=["mixed_packet", "mixed_packet_refinement", "vortex_convergence",
+                                     "vortex_cfl_sweep", "pulse_asymmetry", "pulse_refinement",
+                                     "low_mach_shear", "kelvin_helmholtz"])
+    ap.add_argument("--scheme", default="tai", choices=["tai", "rb"])
+    a = ap.parse_args(argv)
+    fn = globals()[a.name]
+    kw = {"scheme": a.scheme}
+    # RB is linearly unstable above an acoustic CFL of ~0.195 (Sec. 5.2): the paper's
+    # RB settings where the default CFL is higher
+    rb_cfl = {"kelvin_helmholtz": 0.25, "pulse_asymmetry": 0.2, "pulse_refinement": 0.2, "low_mach_shear": 0.19}
+    if a.scheme == "rb" and a.name in rb_cfl:
+        kw["cfl"] = rb_cfl[a.name]
+    r = fn(**kw)
+
+    def plain(v):
+        if isinstance(v, dict):
+            return {k: plain(x) for k, x in v.items() if k not in ("state", "stepper", "history")}
+        if isinstance(v, (list, tuple)):
+            return [plain(x) for x in v]
+        if isinstance(v, (np.floating, np.integer)):
+            return v.item()
+        return v
+
+    out = plain(r)
+    if isinstance(r, dict) and "history" in r:
+        out["history"] = [{"t": t, **d} for t, d in r["history"]]
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(_main())
