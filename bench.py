@@ -224,24 +224,37 @@ def form_adjoint(torch, dev, n, steps, every=20, ndir=8):
     G = xg.grad.detach()
     rng = np.random.default_rng(8)
     rho_planes = [0, 4, 8, 12]
-    eps = 1e-6 * float(x0[rho_planes].abs().max())
-    errs = []
+    scale = float(x0[rho_planes].abs().max())
+    # central differences: the step balancing O(eps^2) truncation against O(u / eps)
+    # rounding is the cube root of the unit roundoff u (times the variable's scale);
+    # 1e-6 of the scale is also reported
+    eps_list = [np.cbrt(np.finfo(np.float64).eps) * scale, 1e-6 * scale]
+    errs = {e: [] for e in eps_list}
+    norm_errs = []
+    gnorm = float(G[rho_planes].norm())
     with torch.no_grad():
         for _ in range(ndir):
             d = torch.zeros_like(x0)
             for pl in rho_planes:
                 d[pl] = torch.from_numpy(rng.normal(size=s0.shape[1:])).to(dev)
-            fd = (J_of_initial(x0 + eps * d) - J_of_initial(x0 - eps * d)) / (2.0 * eps)
             ad = float(torch.sum(G * d))
-            errs.append(abs(fd - ad) / max(abs(ad), 1e-300))
+            for eps in eps_list:
+                fd = (J_of_initial(x0 + eps * d) - J_of_initial(x0 - eps * d)) / (2.0 * eps)
+                errs[eps].append(abs(fd - ad) / max(abs(ad), 1e-300))
+                if eps == eps_list[0]:
+                    norm_errs.append(abs(fd - ad) / (gnorm * float(d.norm())))
+    eps = eps_list[0]
     st.close()
     out = {"nx": n, "ny": n, "dt": dt, "forward_step_ms": t_fwd * 1e3, "adjoint_step_ms": t_adj * 1e3,
            "adjoint_over_forward": t_adj / t_fwd, "gradient_steps": steps, "checkpoint_every": every,
            "gradient_ms": t_grad * 1e3, "forward_rollout_ms": t_fwd_roll * 1e3,
            "gradient_over_forward_rollout": t_grad / t_fwd_roll,
-           "fd_check": {"directions": ndir, "eps": eps, "max_rel_err": max(errs),
+           "fd_check": {"directions": ndir, "eps": eps, "max_rel_err": max(errs[eps]),
+                        "max_err_over_grad_norm": max(norm_errs),
+                        "eps_1e-6": {"eps": eps_list[1], "max_rel_err": max(errs[eps_list[1]])},
                         "subspace": "the four density planes of the initial state"}}
-    log(f"adjoint: ratio {out['adjoint_over_forward']:.2f}, FD max rel {max(errs):.2e}")
+    log(f"adjoint: ratio {out['adjoint_over_forward']:.2f}, FD max rel {max(errs[eps]):.2e} "
+        f"(eps {eps:.2e}; {max(errs[eps_list[1]]):.2e} at eps {eps_list[1]:.2e})")
     return out
 
 
