@@ -233,3 +233,19 @@ def test_gpu_stability_limits(torch_dev):
     g19 = float(np.abs(np.linalg.eigvals(rb.measure(1, 1, 0.19))).max())
     print("RB at 45 degrees, |k h| = 0.56: spectral radius - 1 =", g25 - 1.0, "(nu 0.25),", g19 - 1.0, "(nu 0.19)")
     assert g25 > 1.0 + 1e-6 and g19 < 1.0
+
+
+def test_gpu_power_norm_printed(torch_dev):
+    """Sec. 5.2 from the GPU step: over the 24 x 24 sample of (-pi, pi]^2 (origin
+    included; the lattice of a 24^2 grid) the powers G^k of the measured RB-TAI
+    amplification matrix at nu = 0.25, k <= 1000, reach the printed maximum norm 3.87."""
+    from paper_2605_12915_amd.linear import SymbolMeter
+    m = SymbolMeter(24, 24, "tai", device=torch_dev[1])
+    Gs = np.array([m.measure(mx, my, 0.25) for mx in range(-12, 12) for my in range(-12, 12)])
+    P = np.broadcast_to(np.eye(16), Gs.shape).copy()
+    best = 0.0
+    for _ in range(1000):
+        P = Gs @ P
+        best = max(best, float(np.linalg.norm(P, ord=2, axis=(1, 2)).max()))
+    print("GPU-measured max ||G^k|| (k <= 1000) at nu = 0.25:", best)
+    assert abs(best - 3.87) < 0.005
