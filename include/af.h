@@ -149,7 +149,12 @@ af_status af_time_steps(af_ctx* ctx, const af_state* s, double dt, int32_t nstep
  * autotuner on the first af_step_batch call: every compiled candidate is timed on a
  * copy of the batch's states and the fastest is kept (af_batch_info reports the
  * timings); the environment variable AF_BATCH_TILE=k (0 <= k < 14), read by
- * af_init_batch, fixes candidate k instead.  Candidates (cells x cells / threads per
+ * af_init_batch, fixes candidate k instead.  With AF_BATCH_TUNE_CACHE=path (also read
+ * by af_init_batch) the tuner first looks the batch up in that text file, keyed by
+ * device architecture and compute units, candidate table, point update and the grids'
+ * sizes in order, and takes the recorded choice without timing; otherwise it tunes and
+ * appends a line (an unreadable file is ignored; af_batch_info reports
+ * "tuned_from_cache").  Candidates (cells x cells / threads per
  * workgroup): 32x8/512, 32x8/256, 32x16/512, 32x16/256, 64x8/512, 16x16/256, first
  * in the persistent grid mode (k < 6: CUs x resident workgroups looping over the
  * work list), then in the direct mode (6 <= k < 12: one workgroup per work item),

@@ -47,6 +47,9 @@ struct af_ctx {
     std::vector<af::BatchInst> binst;        // host copy of the descriptors
     std::vector<af::BatchInst> bup;          // descriptors as last uploaded
     int force_cfg = -1;                      // AF_BATCH_TILE: fixed tile configuration, no tuning
+    std::string tune_cache;                  // AF_BATCH_TUNE_CACHE: file of earlier tuning results
+    std::string tune_key;                    // this batch's line key in that file
+    bool tuned_from_cache = false;
     std::string kname;                       // af_dominant_kernel's text for batch contexts
     af::BatchInst* d_binst = nullptr;
     std::vector<void*> bbufs;                // per-instance partner states and compensation planes
@@ -255,6 +258,83 @@ hipError_t batch_tune(af_ctx* c) {
     // the tuning runs leave status bits of scratch data: clear them
     if (e == hipSuccess) e = hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream);
     return e;
+}
+
+// Tuning cache.  One line per tuned batch: its key, the chosen candidate and the
+// per-step times of all candidates.  The key identifies the device (architecture and
+// compute units), the candidate table, the point update and the grid sizes in order:
+// any change there tunes afresh.  A missing, unreadable or malformed file is ignored
+// (the batch is tuned and the line appended); lines with another key are skipped.
+uint64_t fnv1a(uint64_t h, uint64_t v) {
+    for (int b = 0; b < 8; ++b) {
+        h ^= (v >> (8 * b)) & 0xff;
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+std::string batch_tune_key(const af_ctx* c) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        cus = prop.multiProcessorCount;
+    }
+    for (char& ch : arch)
+        if (ch == ' ') ch = '_';
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (int k = 0; k < af::kNumBatchCfgs; ++k) {
+        const af::BatchTileCfg t = af::kBatchCfgs[k];
+        h = fnv1a(h, ((uint64_t)t.tx << 48) ^ ((uint64_t)t.ty << 32) ^ ((uint64_t)t.nt << 8) ^ (t.direct ? 4u : 0u) ^
+                         (uint64_t)t.minw);
+    }
+    for (const af::BatchInst& d : c->binst) h = fnv1a(h, ((uint64_t)(uint32_t)d.nx << 32) | (uint32_t)d.ny);
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "%s/%d/s%d/n%d/%016llx", arch.c_str(), cus, batch_scheme(c), c->nbatch,
+                  (unsigned long long)h);
+    return buf;
+}
+
+bool batch_tune_lookup(af_ctx* c) {
+    std::FILE* f = std::fopen(c->tune_cache.c_str(), "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        char key[200];
+        int cfg = -1, used = 0;
+        if (std::sscanf(line, "%199s %d%n", key, &cfg, &used) != 2 || c->tune_key != key) continue;
+        if (cfg < 0 || cfg >= af::kNumBatchCfgs) continue;
+        double ms[af::kNumBatchCfgs];
+        const char* q = line + used;
+        int k = 0;
+        for (; k < af::kNumBatchCfgs; ++k) {
+            int m = 0;
+            if (std::sscanf(q, "%lf%n", &ms[k], &m) != 1) break;
+            q += m;
+        }
+        if (k != af::kNumBatchCfgs) continue;
+        c->tune_cfg = cfg;              // the last matching line wins
+        for (k = 0; k < af::kNumBatchCfgs; ++k) c->tune_ms[k] = ms[k];
+        found = true;
+    }
+    std::fclose(f);
+    return found;
+}
+
+void batch_tune_store(const af_ctx* c) {
+    std::FILE* f = std::fopen(c->tune_cache.c_str(), "a");
+    if (!f) return;
+    std::string line = c->tune_key + " " + std::to_string(c->tune_cfg);
+    for (int k = 0; k < af::kNumBatchCfgs; ++k) {
+        char t[40];
+        std::snprintf(t, sizeof(t), " %.6f", c->tune_ms[k]);
+        line += t;
+    }
+    line += "\n";
+    std::fputs(line.c_str(), f);
+    std::fclose(f);
 }
 
 // Instantiated graphs are kept per nsteps; past kMaxGraphs distinct values the cache
@@ -563,6 +643,8 @@ af_status af_init_batch(const af_config* cfgs, int32_t n, void* hip_stream, af_c
         const int k = std::atoi(v);
         if (k >= 0 && k < af::kNumBatchCfgs) c->force_cfg = k;
     }
+    if (const char* v = std::getenv("AF_BATCH_TUNE_CACHE"))
+        if (*v) c->tune_cache = v;
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&c->bev[k], hipEventDisableTiming);
@@ -620,7 +702,16 @@ af_status af_step_batch(af_ctx* c, af_state* states, const double* dts, int32_t 
             AF_HIP(batch_build_work(c, c->force_cfg));
             c->tune_cfg = c->force_cfg;
         } else {
-            AF_HIP(batch_tune(c));
+            if (!c->tune_cache.empty()) {
+                c->tune_key = batch_tune_key(c);
+                c->tuned_from_cache = batch_tune_lookup(c);
+            }
+            if (c->tuned_from_cache) {
+                AF_HIP(batch_build_work(c, c->tune_cfg));
+            } else {
+                AF_HIP(batch_tune(c));
+                if (!c->tune_cache.empty()) batch_tune_store(c);
+            }
         }
     }
     AF_HIP(batch_upload(c, c->stream));
@@ -653,6 +744,7 @@ int32_t af_batch_info(af_ctx* c, char* buf, int32_t buflen) {
     } else {
         s += "null";
     }
+    s += std::string(", \"tuned_from_cache\": ") + (c->tuned_from_cache ? "true" : "false");
     s += ", \"candidates\": [";
     for (int k = 0; k < af::kNumBatchCfgs; ++k) {
         const af::BatchTileCfg t = af::kBatchCfgs[k];

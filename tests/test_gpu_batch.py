@@ -230,3 +230,38 @@ def test_batch_64_grids_full_size_one_step(torch_dev, orc):
         worst = max(worst, float((err / tol).max()))
         assert np.all(err <= tol), (P.nx, np.array2string(err / tol, precision=2))
     print("64-grid batch: worst err/tol", worst)
+
+
+def test_tuning_cache(torch_dev, tmp_path, monkeypatch):
+    """AF_BATCH_TUNE_CACHE: the first batch is tuned and recorded; a second batch of the
+    same grids takes the recorded choice without timing (same tile, same timings table,
+    bit-identical results); other grids are tuned afresh and appended; a malformed file
+    is ignored."""
+    torch, dev = torch_dev
+    from paper_2605_12915_amd.stepper import Batch
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("AF_BATCH_TUNE_CACHE", str(cache))
+    monkeypatch.delenv("AF_BATCH_TILE", raising=False)
+    Ps = problems()
+    dts = [P.dt_for_cfl(0.4) for P in Ps]
+
+    def run(ps):
+        xs = pert_states(torch_dev, ps)
+        b = Batch(grids_of(ps), check_errors=True, device=dev)
+        b.step(xs, dts[:len(ps)], 3)
+        torch.cuda.synchronize()
+        return b.info(), xs
+
+    i1, x1 = run(Ps)
+    assert not i1["tuned_from_cache"] and len(cache.read_text().splitlines()) == 1
+    i2, x2 = run(Ps)
+    assert i2["tuned_from_cache"] and i2["chosen"] == i1["chosen"]
+    for a, b in zip(i1["candidates"], i2["candidates"]):
+        assert abs(a["ms_per_step"] - b["ms_per_step"]) < 1e-5
+    for a, b in zip(x1, x2):
+        assert float((a - b).abs().max()) == 0.0
+    i3, _ = run(Ps[:3])
+    assert not i3["tuned_from_cache"] and len(cache.read_text().splitlines()) == 2
+    cache.write_text("garbage line\n" + cache.read_text().split("\n")[0].split()[0] + " 99 1 2\n")
+    i4, _ = run(Ps)
+    assert not i4["tuned_from_cache"]
