@@ -2,7 +2,6 @@
 arithmetic performs for one cell's own work (host build of csrc/count_flops.cpp)."""
 import json
 import os
-import shutil
 import subprocess
 
 import pytest

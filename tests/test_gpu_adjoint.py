@@ -6,7 +6,6 @@
 * dot-product test on a larger grid: <lambda, J v> (oracle JVP) = <J^T lambda, v> (GPU);
 * checkpointed rollout gradient against central finite differences (GPU forward).
 """
-import math
 
 import numpy as np
 import pytest

@@ -1,7 +1,6 @@
 """The paper's experiments run on the GPU step (paper_2605_12915_amd/experiments.py):
 the behaviour the paper reports, and the same runs against the oracle over a short
 horizon at fixed dt."""
-import math
 
 import numpy as np
 import pytest

@@ -15,7 +15,6 @@ point values sampled at the nodes and averages taken as U of the cell-centre val
 (exact averages are not needed for these properties)."""
 import math
 
-import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
