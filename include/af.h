@@ -103,15 +103,31 @@ af_status af_init(const af_config* cfg, void* hip_stream, af_ctx** out);
  * fluxes and the conservative average update (eq. af-average-update).
  * inout: caller-owned device planes, overwritten with the state after nsteps.
  * Errors: AF_ERR_ARG for a bad dt (<= 0 or not finite); with AF_CHECK set, the
- * acoustic-CFL, foot and non-physical checks are read back after the call and, if
- * one fired, *inout is left at the state before the failing call.  Without AF_CHECK
- * the flag is only accumulated on the device (read it with af_read_status). */
+ * acoustic-CFL, foot and non-physical checks are read back after every step and, if
+ * one fired, the call returns its status with *inout (and, for AF_F32, the context's
+ * compensation planes) restored to the input of the call, whichever of the nsteps
+ * steps failed.  The rollback copy is taken on the device before the first step
+ * (allocated by the first such call).  Without AF_CHECK the flag is only accumulated
+ * on the device (read it with af_read_status) and no copy is taken.
+ * AF_F32: the Kahan compensation planes of the average update carry over from one
+ * call to the next only when the call's input is the buffer that holds the previous
+ * call's output (here *inout itself); any other input starts a new trajectory with
+ * zeroed compensation (see also af_reset_trajectory). */
 af_status af_step(af_ctx* ctx, af_state* inout, double dt, int32_t nsteps);
 
 /* One step from `in` to `out` (distinct buffers, both caller-owned); same operation
- * and errors as af_step with nsteps = 1, except that `in` is never modified.
+ * and errors as af_step with nsteps = 1, except that `in` is never modified (on an
+ * error `out` holds the failed step and, with AF_CHECK, an AF_F32 context's
+ * compensation is restored).  AF_F32: the compensation continues when `in` is the
+ * previous call's output buffer (stepping out of a state twice restarts it).
  * AF_ERR_ARG if the two states share a plane pointer. */
 af_status af_step_out(af_ctx* ctx, const af_state* in, af_state* out, double dt);
+
+/* AF_F32 contexts: forget the trajectory, so that the next step starts with zeroed
+ * compensation even if its input buffer is the previous output's (for a caller that
+ * reuses a buffer for unrelated data).  Batch contexts: the same for every grid.
+ * No effect on AF_F64 contexts.  Host-only; AF_ERR_ARG for a null context. */
+af_status af_reset_trajectory(af_ctx* ctx);
 
 /* Read and clear the device status flag accumulated since the last read
  * (synchronises the stream).  *status receives AF_OK or the first error class. */
@@ -174,9 +190,12 @@ af_status af_init_batch(const af_config* cfgs, int32_t n, void* hip_stream, af_c
  * The result for grid q is the one af_step gives on an AF_F32 context of cfgs[q].
  * The library's descriptor copy is re-uploaded (one host synchronisation) only when
  * a state pointer or dt changed since the previous call.  With AF_CHECK in
- * cfgs[0].flags the status of the whole batch is read back after the call (no
- * rollback).  Errors: AF_ERR_ARG for bad pointers or dts, AF_ERR_UNSUPPORTED on a
- * single-grid context (and the single-grid calls return it on a batch context). */
+ * cfgs[0].flags the status of the whole batch is read back after the call and, if a
+ * check fired in any grid at any of the nsteps steps, every grid's state and
+ * compensation are restored to the input of the call (copies taken on the device
+ * before the replay; the first such call allocates one copy per grid).  Errors:
+ * AF_ERR_ARG for bad pointers or dts, AF_ERR_UNSUPPORTED on a single-grid context
+ * (and the single-grid calls return it on a batch context). */
 af_status af_step_batch(af_ctx* ctx, af_state* states, const double* dts, int32_t nsteps);
 
 /* JSON text describing a batch context's work list and tuning (chosen tile shape and

@@ -15,7 +15,7 @@ AF_CHECK, AF_SCHEME_RB = 1, 2
 EXPORTED = [
     "af_init", "af_step", "af_step_out", "af_read_status", "af_step_adjoint", "af_diagnostics",
     "af_time_steps", "af_destroy", "af_status_string", "af_last_hip_error", "af_dominant_kernel",
-    "af_init_batch", "af_step_batch", "af_batch_info",
+    "af_init_batch", "af_step_batch", "af_batch_info", "af_reset_trajectory",
 ]
 
 
@@ -67,6 +67,7 @@ def lib() -> ctypes.CDLL:
         L.af_step_adjoint.argtypes = [P, ctypes.POINTER(AfState), ctypes.POINTER(AfState), ctypes.POINTER(AfState), D]
         L.af_diagnostics.argtypes = [P, ctypes.POINTER(AfState), D, ctypes.POINTER(AfDiag)]
         L.af_time_steps.argtypes = [P, ctypes.POINTER(AfState), D, I32, ctypes.POINTER(D), ctypes.POINTER(D)]
+        L.af_reset_trajectory.argtypes = [P]
         L.af_destroy.argtypes = [P]
         L.af_destroy.restype = None
         L.af_status_string.argtypes = [I32]

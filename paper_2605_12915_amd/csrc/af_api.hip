@@ -15,6 +15,25 @@
 #include "af_batch.h"
 #include "af_internal.h"
 
+namespace af {
+
+// Zero fill by a kernel rather than hipMemsetAsync, so that a caller may capture the
+// enclosing call into a hipGraph (memset nodes are avoided in captured work).
+__global__ void k_zero(unsigned long long* p, size_t n) {
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) p[k] = 0ull;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 8;   // every buffer zeroed here is a whole number of 8-byte words
+    if (n == 0) return hipSuccess;
+    const size_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s,
+                       (unsigned long long*)p, n);
+    return hipGetLastError();
+}
+
+}  // namespace af
+
 namespace {
 
 thread_local int g_last_hip = 0;
@@ -38,7 +57,9 @@ struct af_ctx {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // [0], [1] owned; [2], [3] per-launch timing slots
     bool f32 = false;              // AF_F32 context: float perturbation planes about cfg.bg
     void* comp = nullptr;          // AF_F32: 4 float compensation planes of the average update
-    const void* traj[2] = {nullptr, nullptr};  // AF_F32: buffers of the trajectory the compensation belongs to
+    const void* traj_out = nullptr;  // AF_F32: buffer holding the output the compensation belongs to
+    void* comp_t = nullptr;        // AF_F32: af_time_steps' own compensation planes
+    void* snap = nullptr;          // AF_CHECK: the input state (and compensation) kept for a rollback
     void* adj_scratch = nullptr;   // AF_F64: forward intermediates and reverse accumulators of af_step_adjoint
     int variant = 0;               // 0: fused LDS-tiled kernel, 1: multi-kernel path, 2: two-launch split
     // ---- batching form (af_init_batch) ----
@@ -54,6 +75,7 @@ struct af_ctx {
     af::BatchInst* d_binst = nullptr;
     std::vector<void*> bbufs;                // per-instance partner states and compensation planes
     std::vector<const void*> btraj;          // per-instance state of the current trajectory
+    std::vector<void*> bsnap;                // AF_CHECK: per-instance copy of the input and compensation
     int2* d_work = nullptr;
     int nwork = 0, tune_cfg = -1, grid = 0;
     double tune_ms[af::kNumBatchCfgs] = {};
@@ -144,16 +166,24 @@ hipError_t copy_state(af_ctx* c, void* const dst[16], void* const src[16]) {
     return hipSuccess;
 }
 
-// AF_F32: the Kahan compensation belongs to one trajectory; a state that is neither
-// of the two buffers of the previous call starts a new one (compensation zeroed).
-hipError_t follow_trajectory(af_ctx* c, const void* a, const void* b) {
+// AF_F32: the Kahan compensation belongs to one trajectory.  A call continues it only
+// when its input is the buffer that holds the previous call's output; any other input
+// (including the previous input again) starts a new trajectory with zeroed compensation.
+hipError_t follow_trajectory(af_ctx* c, const void* in, const void* out) {
     if (!c->f32) return hipSuccess;
-    const bool same = (a == c->traj[0] || a == c->traj[1]);
-    c->traj[0] = a;
-    c->traj[1] = b;
+    const bool same = in == c->traj_out;
+    c->traj_out = out;
     if (same) return hipSuccess;
-    return hipMemsetAsync(c->comp, 0, 4 * c->N * sizeof(float), c->stream);
+    return af::launch_zero(c->comp, 4 * c->N * sizeof(float), c->stream);
 }
+
+// AF_CHECK rollback buffer: 16 state planes plus, for AF_F32, the 4 compensation planes.
+hipError_t ensure_snap(af_ctx* c) {
+    if (c->snap) return hipSuccess;
+    return hipMalloc(&c->snap, 16 * c->N * c->elem + (c->f32 ? 4 * c->N * sizeof(float) : 0));
+}
+
+void* snap_comp(af_ctx* c) { return (char*)c->snap + 16 * c->N * c->elem; }
 
 af_status read_status(af_ctx* c, unsigned* bits) {
     unsigned h = 0;
@@ -416,7 +446,7 @@ af_status af_init(const af_config* cfg, void* hip_stream, af_ctx** out) {
     if (c->variant == 2) sbytes = af::scratch_bytes_split_f64(cfg->nx, cfg->ny);
     if (e == hipSuccess && c->f32) e = af::prepare_fused_f32();
     if (e == hipSuccess && c->f32) e = hipMalloc(&c->comp, 4 * c->N * sizeof(float));
-    if (e == hipSuccess && c->f32) e = hipMemsetAsync(c->comp, 0, 4 * c->N * sizeof(float), c->stream);
+    if (e == hipSuccess && c->f32) e = af::launch_zero(c->comp, 4 * c->N * sizeof(float), c->stream);
     if (e == hipSuccess && !c->f32 && c->variant == 0) e = af::prepare_fused_f64();
     if (e == hipSuccess && !c->f32) e = af::prepare_adjoint_f64();
     if (e == hipSuccess && c->variant == 2) e = af::prepare_split_f64();
@@ -450,6 +480,9 @@ void af_destroy(af_ctx* c) {
     if (c->diag_out) (void)hipFree(c->diag_out);
     if (c->comp) (void)hipFree(c->comp);
     if (c->adj_scratch) (void)hipFree(c->adj_scratch);
+    if (c->comp_t) (void)hipFree(c->comp_t);
+    if (c->snap) (void)hipFree(c->snap);
+    for (void* p : c->bsnap) (void)hipFree(p);
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     for (void* p : c->bbufs) (void)hipFree(p);
     if (c->d_binst) (void)hipFree(c->d_binst);
@@ -469,12 +502,23 @@ af_status af_step_out(af_ctx* c, const af_state* in, af_state* out, double dt) {
     void *pi[16], *po[16];
     planes_of(in, pi);
     planes_of(out, po);
+    const bool check = (c->cfg.flags & AF_CHECK) != 0;
     AF_HIP(follow_trajectory(c, pi[0], po[0]));
+    // AF_CHECK on an AF_F32 context: keep the compensation for a rollback
+    if (check && c->f32) {
+        AF_HIP(ensure_snap(c));
+        AF_HIP(hipMemcpyAsync(snap_comp(c), c->comp, 4 * c->N * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    }
     AF_HIP(launch_step(c, pi, po, dt, false));
-    if (c->cfg.flags & AF_CHECK) {
+    if (check) {
         unsigned bits;
         af_status s = read_status(c, &bits);
         if (s != AF_OK) return s;
+        if (bits && c->f32) {
+            AF_HIP(hipMemcpyAsync(c->comp, snap_comp(c), 4 * c->N * sizeof(float), hipMemcpyDeviceToDevice,
+                                  c->stream));
+            AF_HIP(hipStreamSynchronize(c->stream));
+        }
         return status_from_bits(bits);
     }
     return AF_OK;
@@ -486,8 +530,19 @@ af_status af_step(af_ctx* c, af_state* inout, double dt, int32_t nsteps) {
     void *a[16], *b[16];
     planes_of(inout, a);
     planes_of_buffer(c->state2, c->N, c->elem, b);
-    AF_HIP(follow_trajectory(c, a[0], b[0]));
+    // the result ends in *inout: it is the buffer that continues the trajectory
+    AF_HIP(follow_trajectory(c, a[0], a[0]));
     const bool check = (c->cfg.flags & AF_CHECK) != 0;
+    void* snap[16] = {};
+    if (check) {
+        // rollback copy: the input (overwritten from step 1 on) and the compensation
+        AF_HIP(ensure_snap(c));
+        planes_of_buffer(c->snap, c->N, c->elem, snap);
+        if (nsteps > 1) AF_HIP(copy_state(c, snap, a));
+        if (c->f32)
+            AF_HIP(hipMemcpyAsync(snap_comp(c), c->comp, 4 * c->N * sizeof(float), hipMemcpyDeviceToDevice,
+                                  c->stream));
+    }
     for (int s = 0; s < nsteps; ++s) {
         void** src = (s & 1) ? b : a;
         void** dst = (s & 1) ? a : b;
@@ -497,13 +552,26 @@ af_status af_step(af_ctx* c, af_state* inout, double dt, int32_t nsteps) {
             af_status st = read_status(c, &bits);
             if (st != AF_OK) return st;
             if (bits) {
-                if (s & 1) AF_HIP(copy_state(c, a, b));   // keep the last good state in *inout
+                // *inout returns to the input of the call (step 0 writes the partner
+                // buffer only, so it is untouched when step 0 fails)
+                if (s > 0) AF_HIP(copy_state(c, a, snap));
+                if (c->f32)
+                    AF_HIP(hipMemcpyAsync(c->comp, snap_comp(c), 4 * c->N * sizeof(float), hipMemcpyDeviceToDevice,
+                                          c->stream));
                 AF_HIP(hipStreamSynchronize(c->stream));
                 return status_from_bits(bits);
             }
         }
     }
     if (nsteps & 1) AF_HIP(copy_state(c, a, b));
+    return AF_OK;
+}
+
+af_status af_reset_trajectory(af_ctx* c) {
+    if (!c) return AF_ERR_ARG;
+    c->traj_out = nullptr;
+    if (c->nbatch)
+        for (auto& t : c->btraj) t = nullptr;
     return AF_OK;
 }
 
@@ -573,11 +641,19 @@ af_status af_time_steps(af_ctx* c, const af_state* s, double dt, int32_t nsteps,
         return AF_ERR_ARG;
     if (c->nbatch) return AF_ERR_UNSUPPORTED;
     if (!c->state3) AF_HIP(hipMalloc(&c->state3, 16 * c->N * c->elem));
+    if (c->f32 && !c->comp_t) AF_HIP(hipMalloc(&c->comp_t, 4 * c->N * sizeof(float)));
     void *src[16], *a[16], *b[16];
     planes_of(s, src);
     planes_of_buffer(c->state3, c->N, c->elem, a);
     planes_of_buffer(c->state2, c->N, c->elem, b);
     AF_HIP(copy_state(c, a, src));
+    // the timed steps use their own compensation planes: the caller's trajectory is
+    // left as it was
+    void* comp_saved = c->comp;
+    if (c->f32) {
+        AF_HIP(af::launch_zero(c->comp_t, 4 * c->N * sizeof(float), c->stream));
+        c->comp = c->comp_t;
+    }
     // one event pair around every launch of the dominant kernel, on the context stream
     std::vector<hipEvent_t> ev(2 * (size_t)nsteps, nullptr);
     hipError_t e = hipSuccess;
@@ -592,6 +668,7 @@ af_status af_time_steps(af_ctx* c, const af_state* s, double dt, int32_t nsteps,
         e = launch_step(c, x, y, dt, true);
     }
     c->ev[2] = c->ev[3] = nullptr;
+    c->comp = comp_saved;
     if (e == hipSuccess) e = hipEventRecord(c->ev[1], c->stream);
     if (e == hipSuccess) e = hipEventSynchronize(c->ev[1]);
     float ms = 0.f;
@@ -693,7 +770,7 @@ af_status af_step_batch(af_ctx* c, af_state* states, const double* dts, int32_t 
         d.lam1 = (float)(dts[q] / c->bcfg[q].h);
         d.lam0 = (float)(0.5 * dts[q] / c->bcfg[q].h);
         if (c->btraj[q] != p[0]) {   // a new trajectory: fresh compensation
-            AF_HIP(hipMemsetAsync(d.comp, 0, 4 * (size_t)d.nx * d.ny * sizeof(float), c->stream));
+            AF_HIP(af::launch_zero(d.comp, 4 * (size_t)d.nx * d.ny * sizeof(float), c->stream));
             c->btraj[q] = p[0];
         }
     }
@@ -717,16 +794,58 @@ af_status af_step_batch(af_ctx* c, af_state* states, const double* dts, int32_t 
     AF_HIP(batch_upload(c, c->stream));
     hipGraphExec_t gx = nullptr;
     AF_HIP(batch_graph(c, nsteps, &gx));
+    const bool check = (c->cfg.flags & AF_CHECK) != 0;
+    // AF_CHECK: copy every grid's input and compensation for a rollback
+    auto snap_copy = [&](bool restore) -> hipError_t {
+        for (int q = 0; q < c->nbatch; ++q) {
+            const af::BatchInst& d = c->binst[q];
+            const size_t N = (size_t)d.nx * d.ny;
+            float* sp = (float*)c->bsnap[q];
+            for (int k = 0; k < 16; ++k) {
+                void* dst = restore ? (void*)d.S[0][k] : (void*)(sp + k * N);
+                const void* src = restore ? (const void*)(sp + k * N) : (const void*)d.S[0][k];
+                hipError_t e = hipMemcpyAsync(dst, src, N * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
+                if (e != hipSuccess) return e;
+            }
+            void* dst = restore ? (void*)d.comp : (void*)(sp + 16 * N);
+            const void* src = restore ? (const void*)(sp + 16 * N) : (const void*)d.comp;
+            hipError_t e = hipMemcpyAsync(dst, src, 4 * N * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    if (check) {
+        if (c->bsnap.empty()) {
+            for (int q = 0; q < c->nbatch; ++q) {
+                void* p = nullptr;
+                const size_t N = (size_t)c->binst[q].nx * c->binst[q].ny;
+                hipError_t e = hipMalloc(&p, 20 * N * sizeof(float));
+                if (e != hipSuccess) {
+                    for (void* x : c->bsnap) (void)hipFree(x);
+                    c->bsnap.clear();
+                    g_last_hip = (int)e;
+                    return AF_ERR_HIP;
+                }
+                c->bsnap.push_back(p);
+            }
+        }
+        AF_HIP(snap_copy(false));
+    }
     // order the replay after the caller's stream and make the caller's stream wait for it
     AF_HIP(hipEventRecord(c->bev[0], c->stream));
     AF_HIP(hipStreamWaitEvent(c->cap, c->bev[0], 0));
     AF_HIP(hipGraphLaunch(gx, c->cap));
     AF_HIP(hipEventRecord(c->bev[1], c->cap));
     AF_HIP(hipStreamWaitEvent(c->stream, c->bev[1], 0));
-    if (c->cfg.flags & AF_CHECK) {
+    if (check) {
         unsigned bits;
         af_status st = read_status(c, &bits);
         if (st != AF_OK) return st;
+        if (bits) {
+            // every grid returns to the input of the call
+            AF_HIP(snap_copy(true));
+            AF_HIP(hipStreamSynchronize(c->stream));
+        }
         return status_from_bits(bits);
     }
     return AF_OK;

@@ -50,6 +50,9 @@ hipError_t prepare_split_f64();
 size_t scratch_bytes_split_f64(int nx, int ny);
 size_t scratch_bytes_multi_f64(int nx, int ny);
 
+// Zero `bytes` (a multiple of 8) at device pointer p with a fill kernel on stream s.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
 hipError_t launch_diag(const void* const s[16], bool f32, const double bg[4], int nx, int ny, double h,
                        double gamma, double* partials, int npartials, double* out9, hipStream_t stream);
 

@@ -7,6 +7,7 @@ A state is a (16, ny, nx) tensor on the GPU in the plane layout of include/af.h:
 from __future__ import annotations
 
 import ctypes
+import weakref
 from typing import Optional, Sequence
 
 import torch
@@ -49,6 +50,7 @@ class Stepper:
         cfg.flags = (AF_CHECK if check_errors else 0) | (AF_SCHEME_RB if scheme == "rb" else 0)
         self.cfg = cfg
         self.dtype = torch.float64 if precision == "f64" else torch.float32
+        self._last_out = None      # FP32: the tensor holding the output the compensation belongs to
         self._ctx = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             check(L.af_init(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._ctx)),
@@ -71,10 +73,21 @@ class Stepper:
         if t.device != self.device:
             raise ValueError("state on the wrong device")
 
+    def _follow(self, state: torch.Tensor, out: torch.Tensor):
+        """FP32: the library continues the compensation when the input buffer is the
+        previous output's; a different tensor at a reused address starts afresh."""
+        if self.dtype != torch.float32:
+            return
+        last = self._last_out() if self._last_out is not None else None
+        if last is not state:
+            check(_lib.lib().af_reset_trajectory(self._ctx), "af_reset_trajectory")
+        self._last_out = weakref.ref(out)
+
     def step(self, state: torch.Tensor, dt: float, nsteps: int = 1) -> torch.Tensor:
         """Advance in place; returns `state`."""
         self._check_state(state)
         s = state_struct(state)
+        self._follow(state, state)
         check(_lib.lib().af_step(self._ctx, ctypes.byref(s), float(dt), int(nsteps)), "af_step")
         return state
 
@@ -83,6 +96,7 @@ class Stepper:
         out = torch.empty_like(state) if out is None else out
         self._check_state(out)
         a, b = state_struct(state), state_struct(out)
+        self._follow(state, out)
         check(_lib.lib().af_step_out(self._ctx, ctypes.byref(a), ctypes.byref(b), float(dt)), "af_step_out")
         return out
 
@@ -146,6 +160,7 @@ class Batch:
             c.flags = (AF_CHECK if check_errors else 0) | (AF_SCHEME_RB if scheme == "rb" else 0)
         self.cfgs = cfgs
         self.n = n
+        self._last = None          # (weakrefs, data pointers) of the previous call's tensors
         self._ctx = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             check(L.af_init_batch(cfgs, n, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self._ctx)),
@@ -173,6 +188,13 @@ class Batch:
                 raise ValueError(f"instance {q}: expected a (16, {c.ny}, {c.nx}) float32 tensor on {self.device}")
             arr[q] = state_struct(t)
         d = (ctypes.c_double * self.n)(*[float(x) for x in dts])
+        # a new tensor at a buffer address the previous call used would continue the old
+        # compensation in the library (which tracks addresses): start afresh then
+        if self._last is not None:
+            refs, ptrs = self._last
+            if any(r() is not t and t.data_ptr() == p for r, p, t in zip(refs, ptrs, states)):
+                check(_lib.lib().af_reset_trajectory(self._ctx), "af_reset_trajectory")
+        self._last = ([weakref.ref(t) for t in states], [t.data_ptr() for t in states])
         check(_lib.lib().af_step_batch(self._ctx, arr, d, int(nsteps)), "af_step_batch")
         return states
 

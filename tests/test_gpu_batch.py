@@ -206,6 +206,44 @@ def test_batch_errors(torch_dev):
         b.step(xs[:2], dts[:2], 1)
 
 
+def test_batch_check_rolls_back(torch_dev):
+    """AF_CHECK on a batch: a check that fires in one grid after a good step returns
+    every grid (state and compensation) to the input of the call; stepping on from there
+    equals a batch that never made the failed call."""
+    import math
+    torch, dev = torch_dev
+    from paper_2605_12915_amd._lib import AF_ERR_ACOUSTIC_CFL, AfError
+    from paper_2605_12915_amd.stepper import Batch, to_perturbation
+
+    def converging(n):
+        def prim(xv, yv):
+            X, Y = np.meshgrid(xv, yv)
+            return (np.ones_like(X), -0.5 * np.sin(2 * math.pi * X), np.zeros_like(X), np.ones_like(X))
+        return I.Problem("converging", n, n, 0.0, 0.0, 1.0 / n, 1.4, prim, bg=(1.0, 0.0, 0.0, 1.0))
+
+    Ps = problems()[:3] + [converging(32)]
+    # after the half step below, the last grid's acoustic-CFL check fires at the second step
+    dts = [P.dt_for_cfl(0.4) for P in Ps[:3]] + [0.494 * Ps[3].h / math.sqrt(1.4)]
+    x0 = [torch.from_numpy(to_perturbation(P.state(), P.bg, P.gamma)).to(dev) for P in Ps]
+    b = Batch(grids_of(Ps), check_errors=True, device=dev)
+    xs = [x.clone() for x in x0]
+    b.step(xs, [d * 0.5 for d in dts], 1)
+    mid = [x.clone() for x in xs]
+    with pytest.raises(AfError) as e:
+        b.step(xs, dts, 2)
+    assert e.value.code == AF_ERR_ACOUSTIC_CFL
+    for g, w in zip(xs, mid):
+        assert torch.equal(g, w)
+    good = [d * 0.5 for d in dts]
+    b.step(xs, good, 2)
+    c = Batch(grids_of(Ps), check_errors=True, device=dev)
+    ys = [x.clone() for x in x0]
+    c.step(ys, good, 1)
+    c.step(ys, good, 2)
+    for g, w in zip(xs, ys):
+        assert torch.equal(g, w)
+
+
 def test_batch_64_grids_full_size_one_step(torch_dev, orc):
     """The benchmark's batch (64 double shear layers, sizes N in [32, 1024]) in the
     tuned launch configuration, one step, every grid against the oracle."""

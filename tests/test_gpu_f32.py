@@ -70,13 +70,60 @@ def test_f32_pulse_vs_oracle(torch_dev, orc):
     assert err.max() < 2e-5
 
 
-def test_f32_ragged_and_rb(torch_dev, orc):
-    P = I.random_smooth(37, 29, seed=4, amp=0.1, vel=(0.35, -0.25))
+def run_f32_scheme(torch_dev, P, s0, dt, n, bg, scheme):
+    torch, dev = torch_dev
+    from paper_2605_12915_amd.stepper import Stepper, from_perturbation, to_perturbation
+    st = Stepper(P.nx, P.ny, P.h, P.gamma, precision="f32", bg=bg, scheme=scheme, device=dev, check_errors=True)
+    x = torch.from_numpy(to_perturbation(s0, bg, P.gamma)).to(dev)
+    st.step(x, dt, n)
+    torch.cuda.synchronize()
+    return from_perturbation(x.cpu().numpy(), bg, P.gamma)
+
+
+@pytest.mark.parametrize("nx,ny", [(37, 29), (70, 9)])
+def test_f32_ragged_and_rb(torch_dev, orc, nx, ny):
+    """Ragged grids, both point updates: the transported update (TAI) and the additive
+    RB update against the oracle's RB step (scheme 1) at the RB's stable CFL."""
+    P = I.random_smooth(nx, ny, seed=4, amp=0.1, vel=(0.35, -0.25))
     s0 = P.state()
     dt = P.dt_for_cfl(0.4)
     want = orc.run(s0, P.h, P.gamma, dt, 10)
-    got, _, _ = run_f32(torch_dev, P, s0, dt, 10, bg=P.bg)
+    got = run_f32_scheme(torch_dev, P, s0, dt, 10, P.bg, "tai")
     assert pert_err(got, want, s0).max() < 2e-5
+    dt = P.dt_for_cfl(0.15)
+    want = orc.run(s0, P.h, P.gamma, dt, 10, scheme=1)
+    got = run_f32_scheme(torch_dev, P, s0, dt, 10, P.bg, "rb")
+    err = pert_err(got, want, s0)
+    print("f32 RB per-plane error:", np.array2string(err, precision=2))
+    assert err.max() < 2e-5
+
+
+def test_f32_rollback_keeps_compensation(torch_dev):
+    """AF_CHECK on an FP32 context: after a failed call the state and the Kahan
+    compensation are those of the call's input, so the trajectory continues exactly as
+    if the failed call had not been made."""
+    import math
+    torch, dev = torch_dev
+    from paper_2605_12915_amd._lib import AF_ERR_ACOUSTIC_CFL, AfError
+    from paper_2605_12915_amd.stepper import Stepper, to_perturbation
+    P = I.random_smooth(40, 32, seed=5, amp=0.1, vel=(0.3, 0.2))
+    s0 = to_perturbation(P.state(), P.bg, P.gamma)
+    dt = P.dt_for_cfl(0.4)
+    dt_bad = 0.6 * P.h / math.sqrt(1.4)
+    a = Stepper(P.nx, P.ny, P.h, P.gamma, precision="f32", bg=P.bg, device=dev, check_errors=True)
+    x = torch.from_numpy(s0).to(dev)
+    a.step(x, dt, 3)
+    x3 = x.clone()
+    with pytest.raises(AfError) as e:
+        a.step(x, dt_bad, 2)
+    assert e.value.code == AF_ERR_ACOUSTIC_CFL
+    assert torch.equal(x, x3)
+    a.step(x, dt, 3)
+    b = Stepper(P.nx, P.ny, P.h, P.gamma, precision="f32", bg=P.bg, device=dev, check_errors=True)
+    y = torch.from_numpy(s0).to(dev)
+    b.step(y, dt, 3)
+    b.step(y, dt, 3)
+    assert torch.equal(x, y)
 
 
 def test_f32_conservation(torch_dev):

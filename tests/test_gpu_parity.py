@@ -133,6 +133,123 @@ def test_error_statuses(torch_dev):
     assert np.array_equal(x.cpu().numpy(), bad)
 
 
+def _converging(n=32):
+    """Uniform rho = p = 1 with u = -0.5 sin(2 pi x): the compression near x = 0 heats
+    the gas, so that at acoustic CFL 0.494 (0.496) of the initial sound speed the
+    guard c dt / h <= 1/2 holds for two (one) steps and fires at the third (second)."""
+    def prim(xv, yv):
+        X, Y = np.meshgrid(xv, yv)
+        return (np.ones_like(X), -0.5 * np.sin(2 * math.pi * X), np.zeros_like(X), np.ones_like(X))
+    return I.Problem("converging", n, n, 0.0, 0.0, 1.0 / n, 1.4, prim, bg=(1.0, 0.0, 0.0, 1.0))
+
+
+def _oracle_statuses(orc, P, s0, dt, n):
+    x, out = s0, []
+    for _ in range(n):
+        r = orc.step(x, P.h, P.gamma, dt, check=False)
+        if isinstance(r, tuple):
+            x, st = r
+        else:
+            x, st = r, 0
+        out.append(st)
+    return out
+
+
+def test_foot_status(torch_dev, orc):
+    """A supersonic state (u = 3, p = 0.01, c = 0.12) at dt = 0.4 h moves every foot 1.2
+    cells: AF_ERR_FOOT (the kernel clamps the feet to their nodes, so every gather stays
+    in the halo and the launch ends normally) and the input is returned unchanged."""
+    torch, dev = torch_dev
+    from paper_2605_12915_amd._lib import AF_ERR_FOOT, AfError
+    from paper_2605_12915_amd.stepper import Stepper
+    P = I.uniform(12, W=(1.0, 3.0, 0.0, 0.01), ny=10)
+    s0 = P.state()
+    dt = 0.4 * P.h
+    assert _oracle_statuses(orc, P, s0, dt, 1) == [2]           # the oracle's foot status
+    st = Stepper(P.nx, P.ny, P.h, P.gamma, device=dev, check_errors=True)
+    for n in (1, 3):
+        print("foot status, nsteps", n, flush=True)
+        x = torch.from_numpy(s0).to(dev)
+        with pytest.raises(AfError) as e:
+            st.step(x, dt, n)
+        assert e.value.code == AF_ERR_FOOT
+        assert np.array_equal(x.cpu().numpy(), s0)
+    # without AF_CHECK the bit accumulates on the device and af_read_status reports it
+    st2 = Stepper(P.nx, P.ny, P.h, P.gamma, device=dev)
+    x = torch.from_numpy(s0).to(dev)
+    st2.step(x, dt, 1)
+    assert st2.read_status() == AF_ERR_FOOT
+    assert st2.read_status() == 0
+
+
+@pytest.mark.parametrize("r0,nsteps,fails_at", [(0.494, 3, 2), (0.496, 2, 1)])
+def test_check_rolls_back_to_input(torch_dev, orc, r0, nsteps, fails_at):
+    """AF_CHECK with a check that fires after some steps succeeded: the call returns the
+    status and *inout holds the input of the call (not the last good step)."""
+    torch, dev = torch_dev
+    from paper_2605_12915_amd._lib import AF_ERR_ACOUSTIC_CFL, AfError
+    from paper_2605_12915_amd.stepper import Stepper
+    P = _converging()
+    s0 = P.state()
+    dt = r0 * P.h / math.sqrt(1.4)
+    sts = _oracle_statuses(orc, P, s0, dt, nsteps)
+    assert sts[:fails_at] == [0] * fails_at and sts[fails_at] == 1, sts
+    print("rollback case", r0, nsteps, sts, flush=True)
+    st = Stepper(P.nx, P.ny, P.h, P.gamma, device=dev, check_errors=True)
+    x = torch.from_numpy(s0).to(dev)
+    with pytest.raises(AfError) as e:
+        st.step(x, dt, nsteps)
+    assert e.value.code == AF_ERR_ACOUSTIC_CFL
+    assert np.array_equal(x.cpu().numpy(), s0)
+    # the steps before the failing one are fine: stepping them alone matches the oracle
+    # (the v planes are zero up to round-off here: absolute error for them)
+    st.step(x, dt, fails_at)
+    got, want = x.cpu().numpy(), orc.run(s0, P.h, P.gamma, dt, fails_at)
+    scale = np.maximum(np.abs(want).max(axis=(1, 2)), 1.0)
+    assert (np.abs(got - want).max(axis=(1, 2)) / scale).max() <= TOL
+
+
+@pytest.mark.parametrize("vel", [(1.9, -1.7), (1.5, -1.45)])
+def test_general_foot_branch(torch_dev, orc, vel):
+    """Near Mach 2 at dt = 0.4 h / c the half-step and full-step first-stage feet of
+    edge-midpoint targets lie on different sides of the neighbouring face, so those
+    targets leave the shared-cell path of the paired point update and take the general
+    two-stage path (all of them at (1.9, -1.7); a mix of both paths within the same
+    wavefronts at (1.5, -1.45)).  Against the oracle to the FP64 bar."""
+    P = I.random_smooth(40, 36, seed=21, amp=0.08, vel=vel)
+    s0 = P.state()
+    dt = 0.4 * P.h / math.sqrt(1.4)
+    lam1 = dt / P.h
+    u_eh = s0[13]
+    straddle = np.floor(0.5 - 0.5 * lam1 * u_eh) != np.floor(0.5 - lam1 * u_eh)
+    print("general foot branch", vel, "EH targets straddling:", straddle.mean(), flush=True)
+    assert straddle.mean() > 0.5
+    want = orc.run(s0, P.h, P.gamma, dt, 3)
+    got, _ = _run_gpu(torch_dev, P, s0, dt, 3, check_errors=True)
+    assert _err(got, want).max() <= TOL
+
+
+def test_run_twice_bitwise(torch_dev):
+    """The forward step has no atomics in its arithmetic (only the status OR): two runs
+    of the same steps give the same bits, FP64 and FP32."""
+    torch, dev = torch_dev
+    from paper_2605_12915_amd.stepper import Stepper, to_perturbation
+    P = I.fourier_modes(512)
+    s0 = P.state()
+    dt = P.dt_for_cfl(0.4)
+    outs = []
+    for prec in ("f64", "f32"):
+        for rep in range(2):
+            st = Stepper(P.nx, P.ny, P.h, P.gamma, precision=prec, bg=P.bg, device=dev)
+            x = torch.from_numpy(s0 if prec == "f64" else to_perturbation(s0, P.bg, P.gamma)).to(dev)
+            st.step(x, dt, 10)
+            torch.cuda.synchronize()
+            outs.append(x.cpu().numpy())
+            st.close()
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[2], outs[3])
+
+
 def test_diagnostics_match_oracle(torch_dev, orc):
     torch, dev = torch_dev
     from paper_2605_12915_amd.stepper import Stepper
@@ -157,6 +274,20 @@ def test_fourier_modes_2048_one_step(torch_dev, orc):
     got, _ = _run_gpu(torch_dev, P, s0, dt, 1, check_errors=True)
     err = _err(got, want)
     print("2048^2 per-plane error", err.max(), flush=True)
+    assert err.max() <= TOL
+
+
+def test_fourier_modes_2048_20_steps(torch_dev, orc):
+    """The benchmark's 2048^2 flow over 20 steps (its launch configuration), every
+    output against the oracle run on the host cores."""
+    P = I.fourier_modes(2048)
+    s0 = P.state()
+    dt = P.dt_for_cfl(0.4)
+    print("2048^2 Fourier-mode flow: oracle 20 steps ...", flush=True)
+    want = orc.run(s0, P.h, P.gamma, dt, 20)
+    got, _ = _run_gpu(torch_dev, P, s0, dt, 20, check_errors=True)
+    err = _err(got, want)
+    print("2048^2 20 steps per-plane error", err.max(), flush=True)
     assert err.max() <= TOL
 
 
