@@ -52,6 +52,11 @@ def parse():
     ap.add_argument("--adj-steps", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-lite", action="store_true",
+                    help="batch form without the one-by-one comparison and the size classes")
+    ap.add_argument("--adj-dirs", type=int, default=8, help="finite-difference directions of the gradient check")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed repeats of the K headline steps; the median repeat is reported")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=0,
                     help="grid of the oracle sample (0: the headline grid and state itself)")
@@ -107,6 +112,25 @@ def abs_from_pert(torch, x32, bg, gamma):
     return x32.double() + torch.tensor(off, dtype=torch.float64, device=x32.device)[:, None, None]
 
 
+def fp32_roofline(perf, kname, ach, ker_ms, ncell):
+    """FP32 roofline of one launch: algorithmic flops / kernel time against the FP32
+    vector peak, with the stored counter figures of that kernel when they are current
+    (HBM bytes, executed FP32 flops)."""
+    roof = {"bound": "alu", "achieved": ach, "peak": perf.FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / perf.FP32_PEAK_TFLOPS, "kernel": kname, "kernel_ms": ker_ms,
+            "algo_flops_per_cell": perf.ALGO_FLOPS_PER_CELL_F64, "algo_bytes_per_cell": perf.ALGO_BYTES_PER_CELL_F32,
+            "hbm_gbs_algorithmic": perf.ALGO_BYTES_PER_CELL_F32 * ncell / (ker_ms * 1e-3) / 1e9, "traffic": None}
+    tr = perf.stored_traffic(kname)
+    if tr and tr.get("cells_per_launch") == ncell:
+        roof["traffic"] = tr["traffic_bytes_per_launch"]
+        roof["traffic_gbs"] = tr["traffic_bytes_per_launch"] / (ker_ms * 1e-3) / 1e9
+        roof["traffic_frac_of_peak"] = roof["traffic_gbs"] / perf.HBM_PEAK_GBS
+        if tr.get("executed_fp32_flops_per_launch"):
+            ex = tr["executed_fp32_flops_per_launch"] / (ker_ms * 1e-3) / 1e12
+            roof.update({"executed_tflops": ex, "executed_frac_of_peak": ex / perf.FP32_PEAK_TFLOPS})
+    return roof
+
+
 def form_fp32(torch, dev, n, steps):
     from paper_2605_12915_amd import inputs as I
     from paper_2605_12915_amd import perf
@@ -152,9 +176,7 @@ def form_fp32(torch, dev, n, steps):
             "value": ncell * steps / el32 / 1e6, "unit": "Mcell-updates/s",
             "fp64_value": ncell * steps / el64 / 1e6, "speedup_vs_fp64": el64 / el32,
             "kernel": kname, "kernel_ms": ker_ms,
-            "roofline": {"bound": "alu", "achieved": ach, "peak": perf.FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": ach / perf.FP32_PEAK_TFLOPS,
-                         "hbm_gbs_algorithmic": perf.ALGO_BYTES_PER_CELL_F32 * ncell / (ker_ms * 1e-3) / 1e9},
+            "roofline": fp32_roofline(perf, kname, ach, ker_ms, ncell),
             "error_vs_fp64": {"max_l2_rel": worst_l2, "max_linf_rel": worst_linf,
                               "definition": "per plane: ||e||_2 / ||ref - mean(ref)||_2 and max|e| / range(ref)",
                               "per_plane": per},
@@ -170,6 +192,7 @@ def form_adjoint(torch, dev, n, steps, every=20, ndir=8):
     import numpy as np
 
     from paper_2605_12915_amd import inputs as I
+    from paper_2605_12915_amd import perf
     from paper_2605_12915_amd.autodiff import rollout
     from paper_2605_12915_amd.stepper import Stepper
     P = I.acoustic_pulse_adjoint(n)
@@ -187,6 +210,37 @@ def form_adjoint(torch, dev, n, steps, every=20, ndir=8):
     st.adjoint(x0, cot, dt, gout)
     t_fwd = timed(torch, lambda: [st.step_out(x0, dt, y) for _ in range(K)]) / K
     t_adj = timed(torch, lambda: [st.adjoint(x0, cot, dt, gout) for _ in range(K)]) / K
+
+    # the same two sequences between HIP events on the stream the library launches on
+    # (the context borrows torch's current stream)
+    def ev_ms(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / K
+
+    ev_fwd = ev_ms(lambda: [st.step_out(x0, dt, y) for _ in range(K)])
+    ev_adj = ev_ms(lambda: [st.adjoint(x0, cot, dt, gout) for _ in range(K)])
+    ncell = P.nx * P.ny
+    ach = perf.ALGO_FLOPS_PER_CELL_ADJ * ncell / (ev_adj * 1e-3) / 1e12
+    t_alu = perf.ALGO_FLOPS_PER_CELL_ADJ * ncell / (perf.FP64_PEAK_TFLOPS * 1e12)
+    t_hbm = perf.ALGO_BYTES_PER_CELL_ADJ * ncell / (perf.HBM_PEAK_GBS * 1e9)
+    roof = {"bound": "alu" if t_alu >= t_hbm else "hbm", "achieved": ach, "peak": perf.FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": ach / perf.FP64_PEAK_TFLOPS, "kernels": perf.ADJOINT_KERNELS,
+            "step_ms_events": ev_adj, "algo_flops_per_cell": perf.ALGO_FLOPS_PER_CELL_ADJ,
+            "algo_bytes_per_cell": perf.ALGO_BYTES_PER_CELL_ADJ,
+            "hbm_gbs_algorithmic": perf.ALGO_BYTES_PER_CELL_ADJ * ncell / (ev_adj * 1e-3) / 1e9,
+            "t_alu_ms": t_alu * 1e3, "t_hbm_ms": t_hbm * 1e3, "traffic": None}
+    tr = perf.stored_traffic_sum(perf.ADJOINT_KERNELS)
+    if tr:
+        roof["traffic"] = tr["traffic_bytes_per_launch"]
+        roof["traffic_gbs"] = tr["traffic_bytes_per_launch"] / (ev_adj * 1e-3) / 1e9
+        if tr.get("executed_fp64_flops_per_launch"):
+            ex = tr["executed_fp64_flops_per_launch"] / (ev_adj * 1e-3) / 1e12
+            roof.update({"executed_tflops": ex, "executed_frac_of_peak": ex / perf.FP64_PEAK_TFLOPS})
     # annulus acoustic energy from cell-average primitives
     c = (np.arange(n) + 0.5) * P.h
     X, Y = np.meshgrid(c, c)
@@ -245,7 +299,9 @@ def form_adjoint(torch, dev, n, steps, every=20, ndir=8):
     eps = eps_list[0]
     st.close()
     out = {"nx": n, "ny": n, "dt": dt, "forward_step_ms": t_fwd * 1e3, "adjoint_step_ms": t_adj * 1e3,
-           "adjoint_over_forward": t_adj / t_fwd, "gradient_steps": steps, "checkpoint_every": every,
+           "adjoint_over_forward": t_adj / t_fwd, "forward_step_ms_events": ev_fwd, "adjoint_step_ms_events": ev_adj,
+           "adjoint_over_forward_events": ev_adj / ev_fwd, "cotangent": "dense, standard normal in every plane",
+           "roofline": roof, "gradient_steps": steps, "checkpoint_every": every,
            "gradient_ms": t_grad * 1e3, "forward_rollout_ms": t_fwd_roll * 1e3,
            "gradient_over_forward_rollout": t_grad / t_fwd_roll,
            "fd_check": {"directions": ndir, "eps": eps, "max_rel_err": max(errs[eps]),
@@ -260,8 +316,9 @@ def form_adjoint(torch, dev, n, steps, every=20, ndir=8):
 # ---------------------------------------------------------------------------------
 # Batching form
 # ---------------------------------------------------------------------------------
-def form_batch(torch, dev, count, steps, big_fp32_rate):
+def form_batch(torch, dev, count, steps, big_fp32_rate, lite=False):
     from paper_2605_12915_amd import inputs as I
+    from paper_2605_12915_amd import perf
     from paper_2605_12915_amd.stepper import Batch, Stepper, to_perturbation
     sizes = I.batch_sizes(count)
     log(f"batch: generating {count} inputs, {sum(n * n for n in sizes)} cells")
@@ -270,17 +327,49 @@ def form_batch(torch, dev, count, steps, big_fp32_rate):
     xs0 = [torch.from_numpy(to_perturbation(P.state(), P.bg, P.gamma)).to(dev) for P in Ps]
     grids = [dict(nx=P.nx, ny=P.ny, h=P.h, gamma=P.gamma, bg=P.bg) for P in Ps]
 
-    def run_batch(idx, nsteps):
+    def run_batch(idx, nsteps, keep=False):
         b = Batch([grids[k] for k in idx], device=dev)
         xs = [xs0[k].clone() for k in idx]
         b.step(xs, [dts[k] for k in idx], nsteps)          # tuning + capture + first replay
+        kept = [x.clone() for x in xs] if keep else None   # exactly nsteps steps from the input
         el = timed(torch, lambda: b.step(xs, [dts[k] for k in idx], nsteps))
-        info, status = b.info(), b.read_status()
+        info, status, kname = b.info(), b.read_status(), b.dominant_kernel()
         b.close()
-        return sum(sizes[k] ** 2 for k in idx) * nsteps / el / 1e6, el, info, status
+        return sum(sizes[k] ** 2 for k in idx) * nsteps / el / 1e6, el, info, status, kname, kept
 
     allidx = list(range(count))
-    rate, el, info, status = run_batch(allidx, steps)
+    rate, el, info, status, kname, kept = run_batch(allidx, steps, keep=not lite)
+    ncells = sum(n * n for n in sizes)
+    # one launch per step over every grid: the launch duration is the per-step time of
+    # the replayed graph
+    launch_ms = el * 1e3 / steps
+    ach = perf.ALGO_FLOPS_PER_CELL_F64 * ncells / (launch_ms * 1e-3) / 1e12
+    roof = fp32_roofline(perf, kname, ach, launch_ms, ncells)
+    if lite:
+        return {"instances": count, "cells": ncells, "steps": steps, "value": rate,
+                "unit": "Mcell-updates/s", "seconds": el, "status": status, "tuning": info, "roofline": roof}
+    # the batch after exactly `steps` steps against the FP64 GPU path on every grid
+    # (per plane: L2 and L-inf of the difference over the plane's variation, as in the
+    # FP32 form; the worst grid and plane are reported)
+    err = {"max_l2_rel": 0.0, "max_linf_rel": 0.0, "worst_grid": None, "worst_plane": None,
+           "definition": "per grid and plane: ||e||_2 / ||ref - mean(ref)||_2 and max|e| / range(ref), "
+                         "ref = FP64 GPU step from the same initial data"}
+    for k, P in enumerate(Ps):
+        st64 = Stepper(P.nx, P.ny, P.h, P.gamma, device=dev)
+        x64 = torch.from_numpy(P.state()).to(dev)
+        st64.step(x64, dts[k], steps)
+        st64.close()
+        got = abs_from_pert(torch, kept[k], P.bg, P.gamma)
+        for q in range(16):
+            r = x64[q]
+            e = got[q] - r
+            l2 = float(torch.linalg.vector_norm(e) / max(float(torch.linalg.vector_norm(r - r.mean())), 1e-300))
+            linf = float(e.abs().max() / max(float(r.max() - r.min()), 1e-300))
+            if linf > err["max_linf_rel"]:
+                err.update(max_linf_rel=linf, worst_grid=sizes[k], worst_plane=PLANE_NAMES[q])
+            err["max_l2_rel"] = max(err["max_l2_rel"], l2)
+        del x64, got
+    del kept
     # the same instances stepped one by one (one launch per instance and step)
     sts = [Stepper(P.nx, P.ny, P.h, P.gamma, precision="f32", bg=P.bg, device=dev) for P in Ps]
     ys = [x.clone() for x in xs0]
@@ -290,14 +379,13 @@ def form_batch(torch, dev, count, steps, big_fp32_rate):
     el1 = timed(torch, lambda: [s_.step(y, dt, k1) for s_, y, dt in zip(sts, ys, dts)])
     for s_ in sts:
         s_.close()
-    ncells = sum(n * n for n in sizes)
     classes = []
     edges = [32, 64, 128, 256, 512, 1025]
     for lo, hi in zip(edges[:-1], edges[1:]):
         idx = [k for k in allidx if lo <= sizes[k] < hi]
         if not idx:
             continue
-        r_, _, inf_, _ = run_batch(idx, max(100, steps // 5))
+        r_, _, inf_, _, _, _ = run_batch(idx, max(100, steps // 5))
         classes.append({"sizes": [lo, hi - 1], "instances": len(idx), "cells": sum(sizes[k] ** 2 for k in idx),
                         "batched_mcells": r_, "tile": inf_["chosen"],
                         "efficiency_vs_large_grid_fp32": r_ / big_fp32_rate if big_fp32_rate else None})
@@ -307,7 +395,7 @@ def form_batch(torch, dev, count, steps, big_fp32_rate):
            "tuning": info, "one_by_one_mcells": ncells * k1 / el1 / 1e6,
            "speedup_vs_one_by_one": rate / (ncells * k1 / el1 / 1e6),
            "efficiency_vs_large_grid_fp32": rate / big_fp32_rate if big_fp32_rate else None,
-           "size_classes": classes}
+           "size_classes": classes, "roofline": roof, "error_vs_fp64": err}
     log(f"batch: {rate:.0f} Mcell/s aggregate, one-by-one {out['one_by_one_mcells']:.0f}")
     return out
 
@@ -334,7 +422,9 @@ def main():
     torch.cuda.synchronize()
     if args.warmup:
         st.step(x, dt, args.warmup)
-    el = timed(torch, lambda: st.step(x, dt, args.steps))
+    # K steps timed between device synchronisations, repeated; the median repeat is reported
+    els = [timed(torch, lambda: st.step(x, dt, args.steps)) for _ in range(max(1, args.repeats))]
+    el = sorted(els)[len(els) // 2]
     ncell = P.nx * P.ny
     value = ncell * args.steps / el / 1e6
     # dominant-kernel duration from HIP events on the library's stream
@@ -362,7 +452,8 @@ def main():
     line = {
         "metric": "Mcell-updates/s per AF step (FP64 vs FP32) at stated error; adjoint/forward ratio",
         "value": value, "unit": "Mcell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": el * 1e3 / args.steps, "repeats": len(els),
+        "ms_per_step_repeats": [e * 1e3 / args.steps for e in els], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"periodic {P.nx}x{P.ny} FP64 Fourier-mode flow, CFL 0.4, RB-TAI step",
                    "nx": P.nx, "ny": P.ny, "dt": dt},
@@ -405,9 +496,9 @@ def main():
         line["forms"]["fp32"] = form_fp32(torch, dev, args.fp32_n, args.fp32_steps)
         big32 = line["forms"]["fp32"]["gaussian_pulse"]["value"]
     if "adjoint" in forms:
-        line["forms"]["adjoint"] = form_adjoint(torch, dev, args.adj_n, args.adj_steps)
+        line["forms"]["adjoint"] = form_adjoint(torch, dev, args.adj_n, args.adj_steps, ndir=args.adj_dirs)
     if "batch" in forms:
-        line["forms"]["batch"] = form_batch(torch, dev, args.batch_count, args.batch_steps, big32)
+        line["forms"]["batch"] = form_batch(torch, dev, args.batch_count, args.batch_steps, big32, lite=args.batch_lite)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         if args.cpu_sample_n:

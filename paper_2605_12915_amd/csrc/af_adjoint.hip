@@ -24,8 +24,8 @@
 // (the usual convention; the step is continuous across faces because R_h and I_h are).
 #include <hip/hip_runtime.h>
 
+#include "af_adjoint.h"
 #include "af_internal.h"
-#include "af_kernels.h"
 
 namespace af {
 
@@ -85,6 +85,28 @@ struct LdsWin {
 
 struct PlaneList { double* p[40]; };
 
+// Cotangent planes read by cell with a periodic wrap of at most one grid length.
+struct CotAcc {
+    StatePtrs<double> s;
+    int nx, ny;
+    __device__ __forceinline__ double get(int k, int i, int j) const {
+        i = (i < 0) ? i + nx : (i >= nx ? i - nx : i);
+        j = (j < 0) ? j + ny : (j >= ny ? j - ny : j);
+        return s.p[k][(size_t)j * nx + i];
+    }
+};
+
+// One buffer of consecutive planes read by cell (the increments' cotangent).
+struct PlanesAcc {
+    const double* base;
+    int nx, ny;
+    __device__ __forceinline__ double get(int k, int i, int j) const {
+        i = (i < 0) ? i + nx : (i >= nx ? i - nx : i);
+        j = (j < 0) ? j + ny : (j >= ny ? j - ny : j);
+        return base[(size_t)k * nx * ny + (size_t)j * nx + i];
+    }
+};
+
 // The forward state of a block, staged in LDS over the node-cells of its scatter
 // window with the window's plane numbering: point values (0..11), recovered centres
 // (12..15), increments of both durations (16..39).
@@ -119,205 +141,11 @@ __device__ __forceinline__ void flush_window(const LdsWin<NPL, RX, RY>& w, const
     }
 }
 
-// Family of node [a][b] of a cell, the node-cell (dx, dy) of the cell's 2x2 block of
-// node-cells that holds it, and its first plane in the scatter window (point values
-// fam * 4, centre 12).
-__device__ __forceinline__ constexpr int fam_of(int a, int b) {
-    return (a == 1 && b == 1) ? F_C : (a == 1 ? F_EH : (b == 1 ? F_EV : F_V));
-}
-__device__ __forceinline__ constexpr int win_plane(int fam) { return fam == F_C ? 12 : 4 * fam; }
-
 // Periodic index: one shift (offsets of at most one grid length) or a modulo.
 __device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 __device__ __forceinline__ int wrap_any(int v, int n) {
     v %= n;
     return v < 0 ? v + n : v;
-}
-
-__device__ __forceinline__ void lagr(double s, double l[3], double dl[3]) {
-    l[0] = 0.5 * s * (s - 1.0);
-    l[1] = 1.0 - s * s;
-    l[2] = 0.5 * s * (s + 1.0);
-    dl[0] = s - 0.5;
-    dl[1] = -2.0 * s;
-    dl[2] = s + 0.5;
-}
-
-// Flux Jacobians transposed: g += (dF/dW)^T nu, W = (rho, u, v, p).
-__device__ __forceinline__ void flux_x_T(const Prim<double>& w, double gamma, const double nu[4], double g[4]) {
-    const double q2 = 0.5 * (w.u * w.u + w.v * w.v);
-    const double E = w.p / (gamma - 1.0) + w.r * q2;
-    g[0] += nu[0] * w.u + nu[1] * w.u * w.u + nu[2] * w.u * w.v + nu[3] * w.u * q2;
-    g[1] += nu[0] * w.r + nu[1] * 2.0 * w.r * w.u + nu[2] * w.r * w.v + nu[3] * (E + w.p + w.r * w.u * w.u);
-    g[2] += nu[2] * w.r * w.u + nu[3] * w.r * w.u * w.v;
-    g[3] += nu[1] + nu[3] * w.u * gamma / (gamma - 1.0);
-}
-
-__device__ __forceinline__ void flux_y_T(const Prim<double>& w, double gamma, const double nu[4], double g[4]) {
-    const double q2 = 0.5 * (w.u * w.u + w.v * w.v);
-    const double E = w.p / (gamma - 1.0) + w.r * q2;
-    g[0] += nu[0] * w.v + nu[1] * w.u * w.v + nu[2] * w.v * w.v + nu[3] * w.v * q2;
-    g[1] += nu[1] * w.r * w.v + nu[3] * w.r * w.u * w.v;
-    g[2] += nu[0] * w.r + nu[1] * w.r * w.u + nu[2] * 2.0 * w.r * w.v + nu[3] * (E + w.p + w.r * w.v * w.v);
-    g[3] += nu[2] + nu[3] * w.v * gamma / (gamma - 1.0);
-}
-
-// Transposed point update of target FAM at (i, j) for the duration tau = lam h;
-// WP = the target's time-n value.  SCHEME 0: transported update (the increments are
-// interpolated at the foot, the density closure uses c^2 at the foot); SCHEME 1:
-// additive update (the target's own increments, c^2 frozen at the target).
-// The forward value w is recomputed here and its cotangent formed from the flux
-// cotangents: lw = ws * (dF/dW)^T nuF + ws * (dG/dW)^T nuG (+ extra: the cotangent
-// of the new point value itself, for the full step).  The contributions to the
-// target's own node (through the first foot position) are added to gself, those to
-// the nodes of the two foot cells go to the window, one base offset per cell.
-template <int FAM, int SCHEME, class S_, class O_>
-__device__ void point_update_adj(const S_& S, const O_& O, int t, int i, int j, const Prim<double>& WP,
-                                 double gamma, double lam, const double nuF[4], const double nuG[4], double ws,
-                                 const double* extra, double gself[4]) {
-    const double ox = FamOffset<FAM>::ox, oy = FamOffset<FAM>::oy;
-    constexpr int RX = O_::kRX;
-    static_assert(S_::kRX == O_::kRX && S_::kPlane == O_::kPlane, "staged state and window share a layout");
-    unsigned st = 0;
-    // ---- forward recomputation ----
-    int cx1, cy1, cx2, cy2;
-    double xi1, eta1, xi2, eta2;
-    locate(ox - lam * WP.u, ox, cx1, xi1, st);
-    locate(oy - lam * WP.v, oy, cy1, eta1, st);
-    double lx1[3], dlx1[3], ly1[3], dly1[3];
-    lagr(xi1, lx1, dlx1);
-    lagr(eta1, ly1, dly1);
-    double u1 = 0.0, v1 = 0.0, du1x = 0.0, du1y = 0.0, dv1x = 0.0, dv1y = 0.0;
-    const int wb1 = O.base(i + cx1, j + cy1);
-    {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const int f = fam_of(a, b), off = (b == 2 ? RX : 0) + (a == 2 ? 1 : 0);
-                const double nu_ = S.at(win_plane(f) + 1, wb1, off), nv_ = S.at(win_plane(f) + 2, wb1, off);
-                u1 += lx1[a] * ly1[b] * nu_;
-                v1 += lx1[a] * ly1[b] * nv_;
-                du1x += dlx1[a] * ly1[b] * nu_;
-                du1y += lx1[a] * dly1[b] * nu_;
-                dv1x += dlx1[a] * ly1[b] * nv_;
-                dv1y += lx1[a] * dly1[b] * nv_;
-            }
-    }
-    locate(ox - lam * u1, ox, cx2, xi2, st);
-    locate(oy - lam * v1, oy, cy2, eta2, st);
-    double lx2[3], dlx2[3], ly2[3], dly2[3];
-    lagr(xi2, lx2, dlx2);
-    lagr(eta2, ly2, dly2);
-    const int ci = i + cx2, cj = j + cy2;
-    double Wf[4] = {0, 0, 0, 0}, dWx[4] = {0, 0, 0, 0}, dWy[4] = {0, 0, 0, 0};
-    double Df[3] = {0, 0, 0}, dDx[3] = {0, 0, 0}, dDy[3] = {0, 0, 0};
-    const int wb2 = O.base(ci, cj);
-    {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const double w = lx2[a] * ly2[b], wx = dlx2[a] * ly2[b], wy = lx2[a] * dly2[b];
-                const int f = fam_of(a, b), off = (b == 2 ? RX : 0) + (a == 2 ? 1 : 0);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const double v = S.at(win_plane(f) + q, wb2, off);
-                    Wf[q] += w * v; dWx[q] += wx * v; dWy[q] += wy * v;
-                }
-                if constexpr (SCHEME == 0) {
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        const double v = S.at(16 + t * 12 + f * 3 + q, wb2, off);
-                        Df[q] += w * v; dDx[q] += wx * v; dDy[q] += wy * v;
-                    }
-                }
-            }
-    }
-    const int wbP = O.base(i, j);
-    if constexpr (SCHEME == 1) {
-#pragma unroll
-        for (int q = 0; q < 3; ++q) Df[q] = S.at(16 + t * 12 + FAM * 3 + q, wbP, 0);
-    }
-    // ---- reverse ----
-    // compose: rho = rho_f + dp rho_K / (gamma p_K), u = u_f + du, v = v_f + dv, p = p_f + dp,
-    // with K the foot (SCHEME 0) or the target (SCHEME 1)
-    const double rK = SCHEME == 0 ? Wf[0] : WP.r, pK = SCHEME == 0 ? Wf[3] : WP.p;
-    const double qinv = 1.0 / (gamma * pK);
-    double lw[4] = {0.0, 0.0, 0.0, 0.0};
-    {
-        const Prim<double> w{Wf[0] + Df[2] * (rK * qinv), Wf[1] + Df[0], Wf[2] + Df[1], Wf[3] + Df[2]};
-        double nu[4];
-        if constexpr (FAM != F_EH) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) nu[k] = ws * nuF[k];
-            flux_x_T(w, gamma, nu, lw);
-        }
-        if constexpr (FAM != F_EV) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) nu[k] = ws * nuG[k];
-            flux_y_T(w, gamma, nu, lw);
-        }
-        if (extra)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) lw[k] += extra[k];
-    }
-    double lWf[4], lDf[3];
-    lDf[0] = lw[1];
-    lDf[1] = lw[2];
-    lDf[2] = lw[3] + lw[0] * rK * qinv;
-    lWf[1] = lw[1];
-    lWf[2] = lw[2];
-    if constexpr (SCHEME == 0) {
-        lWf[0] = lw[0] * (1.0 + Df[2] * qinv);
-        lWf[3] = lw[3] - lw[0] * Df[2] * rK * qinv / pK;
-    } else {
-        lWf[0] = lw[0];
-        lWf[3] = lw[3];
-        // the frozen rho_K / (gamma p_K) at the target, and its own increments
-        gself[0] += lw[0] * Df[2] * qinv;
-        gself[3] -= lw[0] * Df[2] * rK * qinv / pK;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) O.addb(16 + t * 12 + FAM * 3 + q, wbP, 0, lDf[q]);
-    }
-    // Q2 values at the foot -> nodes of the foot cell
-    {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const double w = lx2[a] * ly2[b];
-                const int f = fam_of(a, b), off = (b == 2 ? RX : 0) + (a == 2 ? 1 : 0);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) O.addb(win_plane(f) + q, wb2, off, w * lWf[q]);
-                if constexpr (SCHEME == 0)
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) O.addb(16 + t * 12 + f * 3 + q, wb2, off, w * lDf[q]);
-            }
-    }
-    // foot position: xi2 = 2 (off - floor(off)) - 1, off = ox - lam u1
-    double lxi2 = 0.0, leta2 = 0.0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) { lxi2 += lWf[q] * dWx[q]; leta2 += lWf[q] * dWy[q]; }
-    if constexpr (SCHEME == 0)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) { lxi2 += lDf[q] * dDx[q]; leta2 += lDf[q] * dDy[q]; }
-    const double lu1 = -2.0 * lam * lxi2, lv1 = -2.0 * lam * leta2;
-    // first stage: u1 = Q2(u) at (xi1, eta1)
-    {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const double w = lx1[a] * ly1[b];
-                const int f = fam_of(a, b), off = (b == 2 ? RX : 0) + (a == 2 ? 1 : 0);
-                O.addb(win_plane(f) + 1, wb1, off, w * lu1);
-                O.addb(win_plane(f) + 2, wb1, off, w * lv1);
-            }
-    }
-    const double lxi1 = lu1 * du1x + lv1 * dv1x, leta1 = lu1 * du1y + lv1 * dv1y;
-    gself[1] += -2.0 * lam * lxi1;
-    gself[2] += -2.0 * lam * leta1;
 }
 
 // Forward intermediates of a TX x TY tile, recomputed from state_n for the reverse
@@ -444,61 +272,6 @@ __global__ void __launch_bounds__(kFNT, 2) k_adj_fwd(StatePtrs<double> prim, dou
     if (st) atomicOr(status, st);
 }
 
-// Reverse sweep of one target (family FAM of node-cell (i, j)): the adjoints of the
-// edge fluxes it feeds, from the averages' cotangents, then of its three time levels
-// (w^n directly, w^{n+1/2} and w^{n+1} through the transposed point update).
-template <int FAM, int SCHEME, class S_, class O_>
-__device__ void point_adj_target(const S_& S, const StatePtrs<double>& cot1, const O_& O, int nx, int ny, int i,
-                                 int j, double gamma, double lam0, double lam1) {
-    const int im = wrap1(i - 1, nx), jm = wrap1(j - 1, ny);
-    auto lU = [&](int a, int b, int k) -> double {
-        return cot1.p[k][(size_t)(b == j ? j : jm) * nx + (a == i ? i : im)];
-    };
-    // cotangents of the time-integrated edge fluxes at this node: F at V and Ev, G at
-    // V and Eh; spatial Simpson weights 1/6 (V, two edges each) and 4/6 (edge midpoints)
-    double nuF[4] = {0, 0, 0, 0}, nuG[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const double muF_ij = lam1 * (lU(i, j, k) - lU(i - 1, j, k));
-        const double muG_ij = lam1 * (lU(i, j, k) - lU(i, j - 1, k));
-        if constexpr (FAM == F_V) {
-            const double muF_ijm = lam1 * (lU(i, j - 1, k) - lU(i - 1, j - 1, k));
-            const double muG_imj = lam1 * (lU(i - 1, j, k) - lU(i - 1, j - 1, k));
-            nuF[k] = (muF_ij + muF_ijm) * (1.0 / 6.0);
-            nuG[k] = (muG_ij + muG_imj) * (1.0 / 6.0);
-        } else if constexpr (FAM == F_EV) {
-            nuF[k] = muF_ij * (4.0 / 6.0);
-        } else {
-            nuG[k] = muG_ij * (4.0 / 6.0);
-        }
-    }
-    // time level n (time-Simpson weight 1/6): the node itself
-    const int wb = O.base(i, j);
-    const Prim<double> w0 = S.node(FAM, wb);
-    double g[4] = {0.0, 0.0, 0.0, 0.0};
-    {
-        double nu[4];
-        if constexpr (FAM != F_EH) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) nu[k] = nuF[k] * (1.0 / 6.0);
-            flux_x_T(w0, gamma, nu, g);
-        }
-        if constexpr (FAM != F_EV) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) nu[k] = nuG[k] * (1.0 / 6.0);
-            flux_y_T(w0, gamma, nu, g);
-        }
-    }
-    // n + 1/2 (weight 4/6) and n + 1 (weight 1/6; also an output of the step)
-    point_update_adj<FAM, SCHEME>(S, O, 0, i, j, w0, gamma, lam0, nuF, nuG, 4.0 / 6.0, nullptr, g);
-    const size_t c = (size_t)j * nx + i;
-    const double extra[4] = {cot1.p[4 + 4 * FAM][c], cot1.p[5 + 4 * FAM][c], cot1.p[6 + 4 * FAM][c],
-                             cot1.p[7 + 4 * FAM][c]};
-    point_update_adj<FAM, SCHEME>(S, O, 1, i, j, w0, gamma, lam1, nuF, nuG, 1.0 / 6.0, extra, g);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) O.addb(win_plane(FAM) + q, wb, 0, g[q]);
-}
-
 // Reverse of the point update, fluxes and average update for a BX x BY block of
 // cells, one thread per (cell, target family).  Feet stay within one cell (guarded),
 // so every read of the forward state and every contribution lies in node-cells
@@ -545,195 +318,13 @@ __global__ void __launch_bounds__(kPNT, 2) k_adj_points(StatePtrs<double> prim, 
     const int cell = (int)threadIdx.x % (kPBX * kPBY), fam = (int)threadIdx.x / (kPBX * kPBY);   // wave-uniform
     const int i = i0 + cell % kPBX, j = j0 + cell / kPBX;
     if (i < nx && j < ny) {
-        if (fam == F_V) point_adj_target<F_V, SCHEME>(S, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
-        else if (fam == F_EV) point_adj_target<F_EV, SCHEME>(S, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
-        else point_adj_target<F_EH, SCHEME>(S, cot1, O, nx, ny, i, j, gamma, lam0, lam1);
+        const CotAcc C1{cot1, nx, ny};
+        if (fam == F_V) point_adj_target<F_V, SCHEME>(S, C1, O, i, j, gamma, lam0, lam1);
+        else if (fam == F_EV) point_adj_target<F_EV, SCHEME>(S, C1, O, i, j, gamma, lam0, lam1);
+        else point_adj_target<F_EH, SCHEME>(S, C1, O, i, j, gamma, lam0, lam1);
     }
     __syncthreads();
     flush_window(O, G, nx, ny);
-}
-
-// Transposed 1-D Lagrange-to-monomial transform (see mono1): (lc0, lc1, lc2) -> (lf0, lf1, lf2).
-template <int XC>
-__device__ __forceinline__ void mono1_T(double c0, double c1, double c2, double& f0, double& f1, double& f2) {
-    if constexpr (XC == 0) { f0 = c0 - 3.0 * c1 + 2.0 * c2; f1 = 4.0 * c1 - 4.0 * c2; f2 = -c1 + 2.0 * c2; }
-    else if constexpr (XC == 1) { f0 = c1 + 2.0 * c2; f1 = -4.0 * c1 - 4.0 * c2; f2 = c0 + 3.0 * c1 + 2.0 * c2; }
-    else { f0 = -c1 + 2.0 * c2; f1 = c0 - 4.0 * c2; f2 = c1 + 2.0 * c2; }
-}
-
-// Transposed wedge: adjoint of the accumulators -> adjoint of the cell's nodal (p, u, v),
-// scattered to the nodes of cell (ci, cj).
-template <int W, int XC, int YC, class O_>
-__device__ __forceinline__ void wedge_adj(const double la[6][4], const O_& O, int ci, int cj) {
-    constexpr int RX = O_::kRX;
-    double lc[3][3][3];
-#pragma unroll
-    for (int v = 0; v < 3; ++v)
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) lc[v][a][b] = 0.0;
-#pragma unroll
-    for (int al = 0; al < 3; ++al)
-#pragma unroll
-        for (int be = 0; be < 3; ++be) {
-            if (al + be == 0) continue;
-            const int m = al + be - 1;
-            const double* B = kBlk[W][al][be];
-            double sp = 0.0, su = 0.0, sv = 0.0;
-            if (B[0] != 0.0) sp += B[0] * la[0][m];
-            if (B[3] != 0.0) sp += B[3] * la[2][m];
-            if (B[6] != 0.0) sp += B[6] * la[4][m];
-            if (B[1] != 0.0) su += B[1] * la[1][m];
-            if (B[4] != 0.0) su += B[4] * la[3][m];
-            if (B[7] != 0.0) su += B[7] * la[5][m];
-            if (B[2] != 0.0) sv += B[2] * la[1][m];
-            if (B[5] != 0.0) sv += B[5] * la[3][m];
-            if (B[8] != 0.0) sv += B[8] * la[5][m];
-            lc[0][al][be] = sp;
-            lc[1][al][be] = su;
-            lc[2][al][be] = sv;
-        }
-    double lf[3][3][3];   // [var][x-node][y-node]
-#pragma unroll
-    for (int v = 0; v < 3; ++v) {
-        double lg[3][3];  // [alpha][y-node]
-#pragma unroll
-        for (int al = 0; al < 3; ++al) mono1_T<YC>(lc[v][al][0], lc[v][al][1], lc[v][al][2], lg[al][0], lg[al][1], lg[al][2]);
-#pragma unroll
-        for (int b = 0; b < 3; ++b) mono1_T<XC>(lg[0][b], lg[1][b], lg[2][b], lf[v][0][b], lf[v][1][b], lf[v][2][b]);
-    }
-    const int wb = O.base(ci, cj);
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const int pl = win_plane(fam_of(a, b)), off = (b == 2 ? RX : 0) + (a == 2 ? 1 : 0);
-            O.addb(pl + 1, wb, off, lf[1][a][b]);
-            O.addb(pl + 2, wb, off, lf[2][a][b]);
-            O.addb(pl + 3, wb, off, lf[0][a][b]);
-        }
-}
-
-template <int FAM, class O_>
-__device__ void incr_adj(const AdjNodes& A, const O_& O, const double* lD, int i, int j, double gamma, double lam0,
-                         double lam1) {
-    const size_t N = (size_t)A.nx * A.ny, k = A.idx(i, j);
-    double li[2][3];
-    bool any = false;
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            li[t][q] = lD[(size_t)(t * 12 + FAM * 3 + q) * N + k];
-            any = any || (li[t][q] != 0.0);
-        }
-    if (!any) return;
-    const Prim<double> W = A.node(FAM, i, j);
-    const double c = sqrt(gamma * W.p / W.r);
-    const double Z = W.r * c, iZ = 1.0 / Z;
-    NodeAcc<double> na;
-    na.zero();
-    node_wedges<FAM>(A, i, j, na);
-    double la[6][4];
-#pragma unroll
-    for (int ch = 0; ch < 6; ++ch)
-#pragma unroll
-        for (int m = 0; m < 4; ++m) la[ch][m] = 0.0;
-    double lc = 0.0, lZ = 0.0, liZ = 0.0;
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const double lam = t ? lam1 : lam0;
-        const double r = c * lam;
-        double s[6], ds[6];
-#pragma unroll
-        for (int ch = 0; ch < 6; ++ch) {
-            s[ch] = ((na.a[ch][3] * r + na.a[ch][2]) * r + na.a[ch][1]) * r + na.a[ch][0];
-            ds[ch] = (3.0 * na.a[ch][3] * r + 2.0 * na.a[ch][2]) * r + na.a[ch][1];
-        }
-        // inc0 = r (s2 iZ + s3), inc1 = r (s4 iZ + s5), inc2 = r (s0 + Z s1)
-        double ls[6];
-        ls[2] = li[t][0] * r * iZ;
-        ls[3] = li[t][0] * r;
-        ls[4] = li[t][1] * r * iZ;
-        ls[5] = li[t][1] * r;
-        ls[0] = li[t][2] * r;
-        ls[1] = li[t][2] * r * Z;
-        double rp = 1.0;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-#pragma unroll
-            for (int ch = 0; ch < 6; ++ch) la[ch][m] += ls[ch] * rp;
-            rp *= r;
-        }
-        const double lr = li[t][0] * (s[2] * iZ + s[3] + r * (ds[2] * iZ + ds[3])) +
-                          li[t][1] * (s[4] * iZ + s[5] + r * (ds[4] * iZ + ds[5])) +
-                          li[t][2] * (s[0] + Z * s[1] + r * (ds[0] + Z * ds[1]));
-        lc += lam * lr;
-        liZ += li[t][0] * r * s[2] + li[t][1] * r * s[4];
-        lZ += li[t][2] * r * s[1];
-    }
-    lZ += -iZ * iZ * liZ;
-    // c = sqrt(gamma p / rho), Z = rho c
-    {
-        const int wb = O.base(i, j);
-        O.addb(win_plane(FAM), wb, 0, lc * (-c / (2.0 * W.r)) + lZ * (0.5 * c));
-        O.addb(win_plane(FAM) + 3, wb, 0, lc * (c / (2.0 * W.p)) + lZ * (W.r * c / (2.0 * W.p)));
-    }
-    if constexpr (FAM == F_V) {
-        wedge_adj<W_V_NE, 0, 0>(la, O, i, j);
-        wedge_adj<W_V_NW, 1, 0>(la, O, i - 1, j);
-        wedge_adj<W_V_SW, 1, 1>(la, O, i - 1, j - 1);
-        wedge_adj<W_V_SE, 0, 1>(la, O, i, j - 1);
-    } else if constexpr (FAM == F_EV) {
-        wedge_adj<W_EV_R, 0, 2>(la, O, i, j);
-        wedge_adj<W_EV_L, 1, 2>(la, O, i - 1, j);
-    } else if constexpr (FAM == F_EH) {
-        wedge_adj<W_EH_U, 2, 0>(la, O, i, j);
-        wedge_adj<W_EH_D, 2, 1>(la, O, i, j - 1);
-    } else {
-        wedge_adj<W_C, 2, 2>(la, O, i, j);
-    }
-}
-
-__device__ __forceinline__ void cons_T(const Prim<double>& w, double gamma, const double lU[4], double g[4]) {
-    // U = (rho, rho u, rho v, p/(gamma-1) + rho (u^2+v^2)/2)
-    const double q2 = 0.5 * (w.u * w.u + w.v * w.v);
-    g[0] = lU[0] + w.u * lU[1] + w.v * lU[2] + q2 * lU[3];
-    g[1] = w.r * lU[1] + w.r * w.u * lU[3];
-    g[2] = w.r * lU[2] + w.r * w.v * lU[3];
-    g[3] = lU[3] / (gamma - 1.0);
-}
-
-// Transposed centre recovery of cell (i, j) for the centre cotangent lW: the averages'
-// cotangent (plane 16 + k of the window, weight 9/4) and the point values of the cell's
-// eight boundary nodes (through U(W) at corners, weight -1/16, and edge midpoints, -1/4).
-template <class O_>
-__device__ __forceinline__ void centre_adj(const AdjNodes& A, const O_& O, int i, int j, const double lW[4],
-                                           double gamma) {
-    const Prim<double> Wc = A.node(F_C, i, j);
-    // W = prim(U_c): rho = U0, u = U1/U0, v = U2/U0, p = (g-1)(U3 - (U1 u + U2 v)/2)
-    const double ir = 1.0 / Wc.r, gm1 = gamma - 1.0;
-    double lU[4];
-    lU[0] = lW[0] - lW[1] * Wc.u * ir - lW[2] * Wc.v * ir + lW[3] * gm1 * 0.5 * (Wc.u * Wc.u + Wc.v * Wc.v);
-    lU[1] = lW[1] * ir - lW[3] * gm1 * Wc.u;
-    lU[2] = lW[2] * ir - lW[3] * gm1 * Wc.v;
-    lU[3] = lW[3] * gm1;
-    // U_c = 9/4 [Ubar - sum_corners U / 36 - sum_edges U / 9]
-    const int wb = O.base(i, j);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) O.addb(16 + k, wb, 0, 2.25 * lU[k]);
-    double lc[4], le[4], g[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) { lc[k] = -lU[k] * (1.0 / 16.0); le[k] = -lU[k] * 0.25; }
-    cons_T(A.node(F_V, i, j), gamma, lc, g);          O.node(F_V, i, j, g);
-    cons_T(A.node(F_V, i + 1, j), gamma, lc, g);      O.node(F_V, i + 1, j, g);
-    cons_T(A.node(F_V, i, j + 1), gamma, lc, g);      O.node(F_V, i, j + 1, g);
-    cons_T(A.node(F_V, i + 1, j + 1), gamma, lc, g);  O.node(F_V, i + 1, j + 1, g);
-    cons_T(A.node(F_EH, i, j), gamma, le, g);         O.node(F_EH, i, j, g);
-    cons_T(A.node(F_EH, i, j + 1), gamma, le, g);     O.node(F_EH, i, j + 1, g);
-    cons_T(A.node(F_EV, i, j), gamma, le, g);         O.node(F_EV, i, j, g);
-    cons_T(A.node(F_EV, i + 1, j), gamma, le, g);     O.node(F_EV, i + 1, j, g);
 }
 
 // Transposed node increments and centre recovery for a BX x BY block of node-cells.
@@ -763,10 +354,11 @@ __global__ void __launch_bounds__(kIBX * kIBY, 2) k_adj_incr(StatePtrs<double> p
         const int i = i0 + (int)threadIdx.x % kIBX;
         const int j = j0 + (int)threadIdx.x / kIBX;
         if (i < nx && j < ny) {
-            incr_adj<F_V>(A, O, lD, i, j, gamma, lam0, lam1);
-            incr_adj<F_EV>(A, O, lD, i, j, gamma, lam0, lam1);
-            incr_adj<F_EH>(A, O, lD, i, j, gamma, lam0, lam1);
-            incr_adj<F_C>(A, O, lD, i, j, gamma, lam0, lam1);
+            const PlanesAcc LD{lD, nx, ny};
+            incr_adj<F_V>(A, LD, O, i, j, gamma, lam0, lam1);
+            incr_adj<F_EV>(A, LD, O, i, j, gamma, lam0, lam1);
+            incr_adj<F_EH>(A, LD, O, i, j, gamma, lam0, lam1);
+            incr_adj<F_C>(A, LD, O, i, j, gamma, lam0, lam1);
         }
     }
     __syncthreads();

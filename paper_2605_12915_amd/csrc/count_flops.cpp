@@ -1,4 +1,5 @@
-// Algorithmic floating-point operation count of one RB-TAI cell-update.
+// Algorithmic floating-point operation counts of one RB-TAI cell-update and of one
+// cell's share of the reverse-mode (adjoint) step.
 //
 // Runs the library's own step arithmetic (af_kernels.h, the functions the kernels
 // call) on the host with an operation-counting scalar, for the work that one cell
@@ -6,6 +7,14 @@
 // both durations, the point updates of its three targets (V, Ev, Eh) for both
 // durations, their time-Simpson fluxes, one x- and one y-edge spatial Simpson flux
 // and the average update.  Halo recomputation of a tiled kernel is not counted.
+// The adjoint count (af_adjoint.h, the functions the adjoint kernels call) covers one
+// cell's share of the reverse step: the forward intermediates recomputed from the
+// time-n state (its centre and its four nodes' increments), the transposed fluxes and
+// point updates of its three targets for both durations (each with the forward foot
+// and Q2 evaluations it recomputes), the transposed increments of its four nodes (each
+// re-forming its wedge sums) and its transposed centre recovery; every scattered
+// contribution counts as one addition.  The kernels' additions of their LDS windows to
+// global memory are not algorithmic work and are not counted.
 // Every +, -, *, /, sqrt counts as one operation; a fused multiply-add counts as two.
 //
 // Build and run (host only):
@@ -30,10 +39,12 @@ inline Cnt& operator+=(Cnt& a, Cnt b) { a = a + b; return a; }
 inline bool operator>(Cnt a, Cnt b) { return a.v > b.v; }
 inline bool operator<(Cnt a, Cnt b) { return a.v < b.v; }
 inline bool operator<=(Cnt a, Cnt b) { return a.v <= b.v; }
+inline bool operator!=(Cnt a, Cnt b) { return a.v != b.v; }
 inline Cnt sqrt(Cnt a) { ++g_sqrt; return Cnt(std::sqrt(a.v)); }
 inline Cnt fabs(Cnt a) { return Cnt(std::fabs(a.v)); }
 inline Cnt floor(Cnt a) { return Cnt(std::floor(a.v)); }
 
+#include "af_adjoint.h"
 #include "af_kernels.h"
 
 using namespace af;
@@ -56,6 +67,29 @@ struct HostInc {
 };
 
 static long total() { return g_add + g_mul + g_div + g_sqrt; }
+
+// Adjoint accessors over a window of node-cells [-2, 6)^2 around cell (2, 2), with the
+// window plane numbering of af_adjoint.h.
+constexpr int kWX = 8;
+struct HostStage {
+    static constexpr int kRX = kWX, kPlane = kWX * kWX;
+    Cnt a[40 * kWX * kWX];
+    Cnt at(int pl, int b, int off) const { return a[b + pl * kPlane + off]; }
+};
+struct HostWin {
+    static constexpr int kRX = kWX, kPlane = kWX * kWX;
+    Cnt* a;
+    int base(int i, int j) const { return (j + 2) * kWX + (i + 2); }
+    void addb(int pl, int b, int off, Cnt v) const { a[b + pl * kPlane + off] = a[b + pl * kPlane + off] + v; }
+    void node(int fam, int i, int j, const Cnt g[4]) const {
+        const int b = fam == F_C ? 12 : 4 * fam, o = base(i, j);
+        for (int q = 0; q < 4; ++q) addb(b + q, o, 0, g[q]);
+    }
+};
+struct HostPlanes {   // cotangent planes by cell, periodic on the 8 x 8 field
+    Cnt v[40][8][8];
+    Cnt get(int k, int i, int j) const { return v[k][(j + 8) % 8][(i + 8) % 8]; }
+};
 
 int main() {
     static HostAcc A;
@@ -124,9 +158,58 @@ int main() {
     }
     long update = total() - c0;
     long all = centre + incV + incE + incC + points + fluxes + update;
+    const long f_add = g_add, f_mul = g_mul, f_div = g_div, f_sqrt = g_sqrt;
+
+    // ---- adjoint: one cell's share of the reverse step ----
+    static HostStage S;
+    static Cnt winbuf[40 * kWX * kWX];
+    static HostPlanes cot, lD;
+    const HostWin O{winbuf};
+    for (int pl = 0; pl < 40; ++pl)
+        for (int y = 0; y < kWX; ++y)
+            for (int x = 0; x < kWX; ++x) {
+                const int i = x - 2, j = y - 2;
+                Cnt v = 1e-3;
+                if (pl < 12) v = A.s[4 + pl][(j + 8) % 8][(i + 8) % 8];
+                else if (pl < 16) v = A.C[pl - 12][(j + 8) % 8][(i + 8) % 8];
+                S.a[pl * kWX * kWX + y * kWX + x] = v;
+            }
+    for (int k = 0; k < 40; ++k)
+        for (int j = 0; j < 8; ++j)
+            for (int i = 0; i < 8; ++i) { cot.v[k][j][i] = 1e-2; lD.v[k][j][i] = 1e-2; }
+    const long a0 = total();
+    // forward intermediates (centre of the cell, increments of its four nodes)
+    recover_centre(Ub, A.node(F_V, 2, 2), A.node(F_V, 3, 2), A.node(F_V, 2, 3), A.node(F_V, 3, 3),
+                   A.node(F_EH, 2, 2), A.node(F_EH, 2, 3), A.node(F_EV, 2, 2), A.node(F_EV, 3, 2), gamma);
+    node_increments<F_V>(A, 2, 2, pol, lam0, lam1, d, st);
+    node_increments<F_EV>(A, 2, 2, pol, lam0, lam1, d, st);
+    node_increments<F_EH>(A, 2, 2, pol, lam0, lam1, d, st);
+    node_increments<F_C>(A, 2, 2, pol, lam0, lam1, d, st);
+    const long adj_fwd = total() - a0;
+    long a1 = total();
+    point_adj_target<F_V, 0>(S, cot, O, 2, 2, gamma, lam0, lam1);
+    point_adj_target<F_EV, 0>(S, cot, O, 2, 2, gamma, lam0, lam1);
+    point_adj_target<F_EH, 0>(S, cot, O, 2, 2, gamma, lam0, lam1);
+    const long adj_points = total() - a1;
+    a1 = total();
+    incr_adj<F_V>(A, lD, O, 2, 2, gamma, lam0, lam1);
+    incr_adj<F_EV>(A, lD, O, 2, 2, gamma, lam0, lam1);
+    incr_adj<F_EH>(A, lD, O, 2, 2, gamma, lam0, lam1);
+    incr_adj<F_C>(A, lD, O, 2, 2, gamma, lam0, lam1);
+    const long adj_incr = total() - a1;
+    a1 = total();
+    const Cnt lW[4] = {1e-2, 1e-2, 1e-2, 1e-2};
+    centre_adj(A, O, 2, 2, lW, gamma);
+    const long adj_centre = total() - a1;
+    const long adj_all = adj_fwd + adj_points + adj_incr + adj_centre;
+    std::fprintf(stderr, "adjoint: forward intermediates %ld, points %ld, increments %ld, centre %ld\n", adj_fwd,
+                 adj_points, adj_incr, adj_centre);
     std::printf("{\"centre\": %ld, \"increments_V\": %ld, \"increments_Ev_Eh\": %ld, \"increments_C\": %ld, "
                 "\"point_updates\": %ld, \"target_fluxes\": %ld, \"edge_fluxes_update\": %ld, "
-                "\"adds\": %ld, \"muls\": %ld, \"divs\": %ld, \"sqrts\": %ld, \"flops_per_cell_update\": %ld}\n",
-                centre, incV, incE, incC, points, fluxes, update, g_add, g_mul, g_div, g_sqrt, all);
+                "\"adds\": %ld, \"muls\": %ld, \"divs\": %ld, \"sqrts\": %ld, "
+                "\"flops_per_cell_update\": %ld, \"adjoint_forward_intermediates\": %ld, \"adjoint_points\": %ld, "
+                "\"adjoint_increments\": %ld, \"adjoint_centre\": %ld, \"adjoint_flops_per_cell\": %ld}\n",
+                centre, incV, incE, incC, points, fluxes, update, f_add, f_mul, f_div, f_sqrt, all, adj_fwd, adj_points,
+                adj_incr, adj_centre, adj_all);
     return 0;
 }

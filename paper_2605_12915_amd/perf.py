@@ -10,6 +10,13 @@ Algorithmic work per cell-update (FP64 step):
     an operation-counting scalar (csrc/count_flops.cpp; a test keeps the figure
     current).  Halo recomputation of a tiled kernel is not algorithmic work.
 
+Algorithmic work per cell of the adjoint step (FP64): 384 B (primal state read,
+cotangent of the output read, cotangent of the input written) and the operation
+count of one cell's share of the reverse step, counted the same way from the
+adjoint kernels' own arithmetic (forward intermediates recomputed, transposed
+point updates with their foot recomputation, transposed increments, transposed
+centre recovery; scattered contributions count as additions).
+
 MI355X peaks: HBM3E 8.0 TB/s; FP64 vector 78.6 TFLOP/s (256 CUs x 4 SIMDs x
 16 lanes x 2 flops x 2.4 GHz); FP32 vector 157.3 TFLOP/s.
 """
@@ -21,6 +28,8 @@ import os
 
 ALGO_FLOPS_PER_CELL_F64 = 4462
 ALGO_BYTES_PER_CELL_F64 = 256
+ALGO_FLOPS_PER_CELL_ADJ = 14293
+ALGO_BYTES_PER_CELL_ADJ = 384
 ALGO_BYTES_PER_CELL_F32 = 160      # 16 float planes each way + 4 compensation planes read and written
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
@@ -31,10 +40,17 @@ ROOT = os.path.dirname(HERE)
 
 # Files whose change invalidates a stored counter measurement of a kernel (its
 # sources, and the build script that holds the compiler flags), relative to the package.
+_STEP = ["csrc/af_fused.h", "csrc/af_kernels.h", "csrc/af_device.h", "csrc/af_blocks.h", "csrc/af_internal.h",
+         "build.py"]
+_ADJ = ["csrc/af_adjoint.hip", "csrc/af_adjoint.h", "csrc/af_kernels.h", "csrc/af_device.h", "csrc/af_blocks.h",
+        "csrc/af_internal.h", "build.py"]
+# the three kernels of one adjoint step (TAI point update)
+ADJOINT_KERNELS = ["af::k_adj_fwd", "af::k_adj_points<0>", "af::k_adj_incr"]
 KERNEL_SOURCES = {
-    "af::k_fused<double, af::PolAbs<double>, 26, 12, 512, 0, false, 1>":
-        ["csrc/af_fused.hip", "csrc/af_fused.h", "csrc/af_kernels.h", "csrc/af_device.h", "csrc/af_blocks.h",
-         "csrc/af_internal.h", "build.py"],
+    "af::k_fused<double, af::PolAbs<double>, 26, 12, 512, 0, false, 1>": ["csrc/af_fused.hip"] + _STEP,
+    "af::k_fused<float, af::PolPert<float>, 24, 13, 512, 0, true, 4>": ["csrc/af_fused_f32.hip"] + _STEP,
+    "af::k_fused_batch_direct<24, 13, 512, 4, 0>": ["csrc/af_batch.hip", "csrc/af_batch.h"] + _STEP,
+    **{k: _ADJ for k in ADJOINT_KERNELS},
 }
 
 
@@ -62,3 +78,15 @@ def stored_traffic(kernel: str):
     if not rec or sha is None or rec.get("source_sha") != sha:
         return None
     return rec
+
+
+def stored_traffic_sum(kernels):
+    """Counter figures of a kernel sequence (one launch of each), summed; None unless
+    every kernel has a current record."""
+    recs = [stored_traffic(k) for k in kernels]
+    if not recs or any(r is None for r in recs):
+        return None
+    out = {"traffic_bytes_per_launch": sum(r["traffic_bytes_per_launch"] for r in recs)}
+    if all(r.get("executed_fp64_flops_per_launch") for r in recs):
+        out["executed_fp64_flops_per_launch"] = sum(r["executed_fp64_flops_per_launch"] for r in recs)
+    return out

@@ -1,5 +1,6 @@
-"""The algorithmic flop count the benchmark reports is the one the kernels'
-arithmetic performs for one cell's own work (host build of csrc/count_flops.cpp)."""
+"""The algorithmic flop counts the benchmark reports are the ones the kernels'
+arithmetic performs for one cell's own work, forward step and adjoint step (host
+build of csrc/count_flops.cpp)."""
 import json
 import os
 import subprocess
@@ -19,6 +20,12 @@ def test_flop_count_current(tmp_path):
     out = json.loads(subprocess.run([exe], check=True, capture_output=True, text=True).stdout)
     assert out["flops_per_cell_update"] == perf.ALGO_FLOPS_PER_CELL_F64
     assert out["sqrts"] == 4 and out["divs"] > 0
+    # the adjoint's share per cell: its parts add up, and it re-forms the forward
+    # intermediates (centre and increments) exactly once
+    parts = ("adjoint_forward_intermediates", "adjoint_points", "adjoint_increments", "adjoint_centre")
+    assert sum(out[k] for k in parts) == out["adjoint_flops_per_cell"] == perf.ALGO_FLOPS_PER_CELL_ADJ
+    assert out["adjoint_forward_intermediates"] == (out["centre"] + out["increments_V"] + out["increments_Ev_Eh"]
+                                                    + out["increments_C"])
 
 
 def test_dominant_kernel_has_tracked_sources():
