@@ -42,7 +42,8 @@ enum {
     AF_ERR_ACOUSTIC_CFL = 3, /* some node has c_K dt / h > 1/2 (node-centred wedges invalid) */
     AF_ERR_FOOT = 4,         /* some convective foot moved one cell or more */
     AF_ERR_NONPHYSICAL = 5,  /* rho <= 0 or p <= 0 at a node or recovered centre, or NaN */
-    AF_ERR_UNSUPPORTED = 6   /* operation not available for this context's precision */
+    AF_ERR_UNSUPPORTED = 6,  /* operation not available for this context's precision */
+    AF_ERR_SCRATCH = 7       /* grid larger than the fixed scratch of af_step_adjoint_noalloc */
 };
 
 enum { AF_F64 = 0, AF_F32 = 1 };
@@ -145,6 +146,23 @@ af_status af_read_status(af_ctx* ctx, af_status* status);
  * (a floor) is taken as zero. */
 af_status af_step_adjoint(af_ctx* ctx, const af_state* primal_n, const af_state* cot_np1,
                           af_state* cot_n, double dt);
+
+/* Allocation-free form of af_step_adjoint, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  Same operation, arguments and errors as af_step_adjoint, without a
+ * context: cfg (read only; precision must be AF_F64, flags may hold AF_SCHEME_RB and
+ * AF_CHECK) and hip_stream (borrowed; NULL for the null stream) stand in for it.
+ * The call allocates nothing: the 56 scratch planes and the status word live in a
+ * static device array that every GPU loading the library holds for the life of the
+ * process, sized for grids of at most 65536 cells (nx ny <= 2^16, e.g. 256 x 256;
+ * 29.4 MB).  Larger grids return AF_ERR_SCRATCH before any work is enqueued.  All
+ * calls on one GPU share that array and the array keeps the last call's contents: the
+ * kernels zero what must start at zero, but calls that overlap on one GPU (different
+ * streams or threads without ordering) race and give wrong results.  Asynchronous on
+ * hip_stream; with AF_CHECK the call synchronises the stream and returns the step's
+ * acoustic-CFL, foot and non-physical status. */
+af_status af_step_adjoint_noalloc(const af_config* cfg, void* hip_stream, const af_state* primal_n,
+                                  const af_state* cot_np1, af_state* cot_n, double dt);
 
 /* Diagnostics of a state (Sec. 6, opening paragraph: CFL and entropy; Sec. 3:
  * conservation), reduced in FP64 on the device.  Synchronous: returns when *out is

@@ -8,7 +8,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaf.so")
 
-AF_OK, AF_ERR_ARG, AF_ERR_HIP, AF_ERR_ACOUSTIC_CFL, AF_ERR_FOOT, AF_ERR_NONPHYSICAL, AF_ERR_UNSUPPORTED = range(7)
+(AF_OK, AF_ERR_ARG, AF_ERR_HIP, AF_ERR_ACOUSTIC_CFL, AF_ERR_FOOT, AF_ERR_NONPHYSICAL, AF_ERR_UNSUPPORTED,
+ AF_ERR_SCRATCH) = range(8)
 AF_F64, AF_F32 = 0, 1
 AF_CHECK, AF_SCHEME_RB = 1, 2
 
@@ -16,6 +17,7 @@ EXPORTED = [
     "af_init", "af_step", "af_step_out", "af_read_status", "af_step_adjoint", "af_diagnostics",
     "af_time_steps", "af_destroy", "af_status_string", "af_last_hip_error", "af_dominant_kernel",
     "af_init_batch", "af_step_batch", "af_batch_info", "af_reset_trajectory",
+    "af_step_adjoint_noalloc",
 ]
 
 
@@ -68,6 +70,8 @@ def lib() -> ctypes.CDLL:
         L.af_diagnostics.argtypes = [P, ctypes.POINTER(AfState), D, ctypes.POINTER(AfDiag)]
         L.af_time_steps.argtypes = [P, ctypes.POINTER(AfState), D, I32, ctypes.POINTER(D), ctypes.POINTER(D)]
         L.af_reset_trajectory.argtypes = [P]
+        L.af_step_adjoint_noalloc.argtypes = [ctypes.POINTER(AfConfig), P, ctypes.POINTER(AfState),
+                                              ctypes.POINTER(AfState), ctypes.POINTER(AfState), D]
         L.af_destroy.argtypes = [P]
         L.af_destroy.restype = None
         L.af_status_string.argtypes = [I32]

@@ -24,6 +24,8 @@
 // (the usual convention; the step is continuous across faces because R_h and I_h are).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "af_adjoint.h"
 #include "af_internal.h"
 
@@ -443,5 +445,55 @@ hipError_t prepare_adjoint_f64() {
 }
 
 size_t scratch_bytes_adjoint_f64(int nx, int ny) { return (size_t)nx * ny * (4 + 24 + 4 + 24) * sizeof(double); }
+
+// ---- allocation-free form of the adjoint step ------------------------------------
+// The scratch of launch_adjoint_f64 (56 planes: forward intermediates and reverse
+// accumulators) and the status word, in a file-scope device array sized for grids of
+// up to kNoallocMaxCells cells.  Every device that loads the library holds its own copy
+// for the life of the process.  Only its device address (hipGetSymbolAddress, taken
+// once per device with that device current) is ever handed to kernels; the array's name
+// in host code is a host-side stand-in.  k_adj_fwd zeroes every accumulation plane for
+// the grid's cells itself; the status word is cleared by a fill kernel on each call.
+constexpr size_t kNoallocStatusWords = 32;   // 256 bytes: the planes stay 256-byte aligned
+static __device__ __align__(256) double scratch[kNoallocStatusWords + kNoallocMaxCells * 56];
+
+static_assert(sizeof(scratch) == kNoallocBytes, "scratch size as declared in af_internal.h");
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mutex;
+void* g_noalloc_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_ptr(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        // the point kernel's LDS exceeds the default limit: allowed once per device here
+        e = prepare_adjoint_f64();
+        if (e != hipSuccess) return e;
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = g_noalloc_ptr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_adjoint_noalloc(StepArgs a, const void* const cot1[16], void* const cot0[16]) {
+    void* p = nullptr;
+    hipError_t e = noalloc_scratch_ptr(&p);
+    if (e != hipSuccess) return e;
+    a.status = (unsigned*)p;
+    a.scratch = (double*)p + kNoallocStatusWords;
+    e = launch_zero(p, kNoallocStatusWords * sizeof(double), a.stream);
+    if (e != hipSuccess) return e;
+    return launch_adjoint_f64(a, cot1, cot0);
+}
 
 }  // namespace af

@@ -408,6 +408,7 @@ const char* af_status_string(af_status s) {
         case AF_ERR_FOOT: return "convective foot moved one cell or more";
         case AF_ERR_NONPHYSICAL: return "non-physical state (rho <= 0, p <= 0 or NaN)";
         case AF_ERR_UNSUPPORTED: return "operation not supported for this precision";
+        case AF_ERR_SCRATCH: return "grid larger than the static scratch of the allocation-free entry point";
         default: return "unknown status";
     }
 }
@@ -607,6 +608,41 @@ af_status af_step_adjoint(af_ctx* c, const af_state* primal_n, const af_state* c
     planes_of(cot_np1, p1);
     planes_of(cot_n, p0);
     AF_HIP(af::launch_adjoint_f64(a, p1, p0));
+    return AF_OK;
+}
+
+af_status af_step_adjoint_noalloc(const af_config* cfg, void* hip_stream, const af_state* primal_n,
+                                  const af_state* cot_np1, af_state* cot_n, double dt) {
+    if (!cfg || !state_ok(primal_n) || !state_ok(cot_np1) || !state_ok(cot_n) || !(dt > 0.0) || !std::isfinite(dt))
+        return AF_ERR_ARG;
+    if (cfg->nx < 4 || cfg->ny < 4 || !(cfg->h > 0.0) || !(cfg->gamma > 1.0) || !std::isfinite(cfg->h) ||
+        !std::isfinite(cfg->gamma))
+        return AF_ERR_ARG;
+    if (share_plane(cot_n, cot_np1) || share_plane(cot_n, primal_n)) return AF_ERR_ARG;
+    if (cfg->precision != AF_F64) return AF_ERR_UNSUPPORTED;
+    if ((uint64_t)cfg->nx * (uint64_t)cfg->ny > af::kNoallocMaxCells) return AF_ERR_SCRATCH;
+    af::StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nx = cfg->nx;
+    a.ny = cfg->ny;
+    a.h = cfg->h;
+    a.gamma = cfg->gamma;
+    a.dt = dt;
+    a.scheme = (cfg->flags & AF_SCHEME_RB) ? 1 : 0;
+    a.stream = (hipStream_t)hip_stream;
+    planes_of(primal_n, a.in);
+    void *p1[16], *p0[16];
+    planes_of(cot_np1, p1);
+    planes_of(cot_n, p0);
+    AF_HIP(af::launch_adjoint_noalloc(a, p1, p0));
+    if (cfg->flags & AF_CHECK) {
+        void* sp = nullptr;
+        AF_HIP(af::noalloc_scratch_ptr(&sp));
+        unsigned h = 0;
+        AF_HIP(hipMemcpyAsync(&h, sp, sizeof(unsigned), hipMemcpyDeviceToHost, a.stream));
+        AF_HIP(hipStreamSynchronize(a.stream));
+        return status_from_bits(h);
+    }
     return AF_OK;
 }
 

@@ -39,6 +39,13 @@ hipError_t launch_diag_final(const double* partials, int n, double* out9, hipStr
 hipError_t launch_step_multi_f64(const StepArgs& a);
 hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1[16], void* const cot0[16]);
 size_t scratch_bytes_adjoint_f64(int nx, int ny);
+// Allocation-free adjoint: the scratch lives in a static device array of fixed size
+// (grids of at most kNoallocMaxCells cells); a.scratch and a.status are replaced.
+constexpr size_t kNoallocMaxCells = size_t(1) << 16;
+constexpr size_t kNoallocBytes = (32 + kNoallocMaxCells * 56) * sizeof(double);
+hipError_t launch_adjoint_noalloc(StepArgs a, const void* const cot1[16], void* const cot0[16]);
+// The device address of that array on the current device (looked up once per device).
+hipError_t noalloc_scratch_ptr(void** out);
 hipError_t launch_step_fused_f64(const StepArgs& a);
 hipError_t launch_step_fused_f32(const StepArgs& a);
 hipError_t prepare_fused_f32();
