@@ -928,12 +928,12 @@ const char* af_dominant_kernel(af_ctx* c) {
     }
     const bool rb = c && (c->cfg.flags & AF_SCHEME_RB);
     if (c && c->f32)
-        return rb ? "af::k_fused<float, af::PolPert<float>, 24, 13, 512, 1, true, 4>"
-                  : "af::k_fused<float, af::PolPert<float>, 24, 13, 512, 0, true, 4>";
+        return rb ? "af::k_fused<float, af::PolPert<float>, 24, 13, 512, 1, true, 4, 0, false>"
+                  : "af::k_fused<float, af::PolPert<float>, 24, 13, 512, 0, true, 4, 0, false>";
     if (c && c->variant == 1) return "af_step multi-kernel sequence";
     if (c && c->variant == 2) return rb ? "af::k_points_update<32, 8, 512, 1>" : "af::k_points_update<32, 8, 512, 0>";
-    return rb ? "af::k_fused<double, af::PolAbs<double>, 26, 12, 512, 1, false, 1>"
-              : "af::k_fused<double, af::PolAbs<double>, 26, 12, 512, 0, false, 1>";
+    return rb ? "af::k_fused<double, af::PolAbs<double>, 31, 10, 512, 1, false, 1, 32, true>"
+              : "af::k_fused<double, af::PolAbs<double>, 31, 10, 512, 0, false, 1, 32, true>";
 }
 
 }  // extern "C"

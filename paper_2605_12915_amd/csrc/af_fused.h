@@ -86,7 +86,14 @@ __device__ __forceinline__ int wrap_win(int v, int n, bool one) {
 //
 // SP: any type with a member p such that p[k] is plane k's pointer (StatePtrs, or a
 // view of a descriptor in global memory whose pointers are loaded where used).
-template <class T, class Pol, int TX, int TY, int NT, int SCHEME, bool KAHAN, class SP>
+// RW: phase 3 lays each target family's items out in rows of RW lanes (0: rows as
+// wide as the family's own row of targets).  With RW a multiple of 16, the lanes that
+// the LDS serves together read consecutive words of one row (no bank conflicts for
+// feet at a common offset).  DYN: the family of a target is a run-time value, so a
+// wavefront holding targets of two families runs one instruction stream instead of
+// both families' code one after the other.
+template <class T, class Pol, int TX, int TY, int NT, int SCHEME, bool KAHAN, int RW = 0, bool DYN = false,
+          class SP>
 __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in, const SP& out,
                                            T* comp, int nx, int ny, int i0, int j0, const Pol pol, T lam0, T lam1,
                                            unsigned& st) {
@@ -186,9 +193,19 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
     __syncthreads();
 
     // ---- phase 3: point updates of targets in node-cells [0, T] ----------------------
-    constexpr int NV_ = Tile::VX * Tile::VY, NE_ = Tile::VX * TY, NH_ = TX * Tile::VY;
+    // items: V targets (VX x VY), then Ev (VX x TY), then Eh (TX x VY), each family in
+    // rows of WV / WE / WH lanes (lanes past the family's row width idle)
+    constexpr int WV = RW ? RW : Tile::VX, WE = RW ? RW : Tile::VX, WH = RW ? RW : TX;
+    static_assert(WV >= Tile::VX && WH >= TX, "item rows hold a row of targets");
+    constexpr int NV_ = WV * Tile::VY, NE_ = WE * TY, NH_ = WH * Tile::VY;
     constexpr int NITEMS = NV_ + NE_ + NH_;
     constexpr int ROUNDS = (NITEMS + NT - 1) / NT;
+    auto decode = [&](int e, int& fam, int& x, int& y) -> bool {
+        if (e < NV_) { fam = F_V; x = e % WV; y = e / WV; return x < Tile::VX; }
+        if (e < NV_ + NE_) { fam = F_EV; x = (e - NV_) % WE; y = (e - NV_) / WE; return x < Tile::VX; }
+        fam = F_EH; x = (e - NV_ - NE_) % WH; y = (e - NV_ - NE_) / WH;
+        return x < TX;
+    };
     T fres[ROUNDS][8];
     {
         LdsAcc<T, TX, TY> A{&L};
@@ -198,15 +215,21 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
             const int e = r * NT + tid;
             if (e >= NITEMS) continue;
             int fam, x, y;
-            if (e < NV_) { fam = F_V; x = e % Tile::VX; y = e / Tile::VX; }
-            else if (e < NV_ + NE_) { fam = F_EV; x = (e - NV_) % Tile::VX; y = (e - NV_) / Tile::VX; }
-            else { fam = F_EH; x = (e - NV_ - NE_) % TX; y = (e - NV_ - NE_) / TX; }
+            if (!decode(e, fam, x, y)) continue;
             Prim<T> w0, wh, w1;
             // new point values of owned nodes (plane indices kept static: a dynamic
             // index into the pointer set would put it in private memory)
             const bool own = x < TX && y < TY && i0 + x < nx && j0 + y < ny;
             const size_t g = own ? (size_t)(j0 + y) * nx + (i0 + x) : 0;
-            if (fam == F_V) {
+            if constexpr (DYN) {
+                w0 = A.node(fam, x, y);
+                point_update_pair_f<SCHEME>(A, D0, D1, fam, x, y, pol, lam0, lam1, st, wh, w1);
+                if (own) {
+                    if (fam == F_V) store_prim<4>(out, g, w1);
+                    else if (fam == F_EV) store_prim<8>(out, g, w1);
+                    else store_prim<12>(out, g, w1);
+                }
+            } else if (fam == F_V) {
                 w0 = A.node(F_V, x, y);
                 point_update_pair<F_V, SCHEME>(A, D0, D1, x, y, pol, lam0, lam1, st, wh, w1);
                 if (own) store_prim<4>(out, g, w1);
@@ -262,16 +285,15 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
     for (int r = 0; r < ROUNDS; ++r) {
         const int e = r * NT + tid;
         if (e >= NITEMS) continue;
-        if (e < NV_) {
-            const int x = e % Tile::VX, y = e / Tile::VX;
+        int fam, x, y;
+        if (!decode(e, fam, x, y)) continue;
+        if (fam == F_V) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) L.F.FV[k][y][x] = fres[r][k];
-        } else if (e < NV_ + NE_) {
-            const int x = (e - NV_) % Tile::VX, y = (e - NV_) / Tile::VX;
+        } else if (fam == F_EV) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) L.F.FE[k][y][x] = fres[r][k];
         } else {
-            const int x = (e - NV_ - NE_) % TX, y = (e - NV_ - NE_) / TX;
 #pragma unroll
             for (int k = 0; k < 4; ++k) L.F.GE[k][y][x] = fres[r][k];
         }
@@ -340,7 +362,8 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
 // ---- single-grid kernel: one tile per workgroup --------------------------------------
 // MINW: minimum wavefronts per SIMD the register allocation must allow (1: no
 // constraint beyond the workgroup size; 4 at 512 threads: two workgroups per CU).
-template <class T, class Pol, int TX, int TY, int NT, int SCHEME, bool KAHAN, int MINW = 1>
+template <class T, class Pol, int TX, int TY, int NT, int SCHEME, bool KAHAN, int MINW = 1, int RW = 0,
+          bool DYN = false>
 __global__ void __launch_bounds__(NT, MINW) k_fused(StatePtrs<T> in, StatePtrs<T> out, T* comp, int nx, int ny,
                                               int tiles_x, int ntiles, Pol pol, T lam0, T lam1, unsigned* status) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -355,13 +378,13 @@ __global__ void __launch_bounds__(NT, MINW) k_fused(StatePtrs<T> in, StatePtrs<T
         tile = base + (b >> 3);
     }
     unsigned st = 0;
-    fused_tile<T, Pol, TX, TY, NT, SCHEME, KAHAN>(L, in, out, comp, nx, ny, (tile % tiles_x) * TX,
-                                                  (tile / tiles_x) * TY, pol, lam0, lam1, st);
+    fused_tile<T, Pol, TX, TY, NT, SCHEME, KAHAN, RW, DYN>(L, in, out, comp, nx, ny, (tile % tiles_x) * TX,
+                                                           (tile / tiles_x) * TY, pol, lam0, lam1, st);
     if (st) atomicOr(status, st);
 }
 
 
-template <class T, class Pol, int TX, int TY, int NT, bool KAHAN, int MINW = 1>
+template <class T, class Pol, int TX, int TY, int NT, bool KAHAN, int MINW = 1, int RW = 0, bool DYN = false>
 hipError_t launch_fused(const StepArgs& a, const Pol& pol) {
     StatePtrs<T> in, out;
     for (int k = 0; k < 16; ++k) { in.p[k] = (T*)a.in[k]; out.p[k] = (T*)a.out[k]; }
@@ -372,22 +395,22 @@ hipError_t launch_fused(const StepArgs& a, const Pol& pol) {
     T* comp = (T*)a.comp;
     if (a.ev_begin) (void)hipEventRecord(a.ev_begin, a.stream);
     if (a.scheme == 0)
-        hipLaunchKernelGGL((k_fused<T, Pol, TX, TY, NT, 0, KAHAN, MINW>), dim3(ntiles), dim3(NT), lds, a.stream, in, out, comp,
+        hipLaunchKernelGGL((k_fused<T, Pol, TX, TY, NT, 0, KAHAN, MINW, RW, DYN>), dim3(ntiles), dim3(NT), lds, a.stream, in, out, comp,
                            a.nx, a.ny, tiles_x, ntiles, pol, lam0, lam1, a.status);
     else
-        hipLaunchKernelGGL((k_fused<T, Pol, TX, TY, NT, 1, KAHAN, MINW>), dim3(ntiles), dim3(NT), lds, a.stream, in, out, comp,
+        hipLaunchKernelGGL((k_fused<T, Pol, TX, TY, NT, 1, KAHAN, MINW, RW, DYN>), dim3(ntiles), dim3(NT), lds, a.stream, in, out, comp,
                            a.nx, a.ny, tiles_x, ntiles, pol, lam0, lam1, a.status);
     if (a.ev_end) (void)hipEventRecord(a.ev_end, a.stream);
     return hipGetLastError();
 }
 
-template <class T, class Pol, int TX, int TY, int NT, bool KAHAN, int MINW = 1>
+template <class T, class Pol, int TX, int TY, int NT, bool KAHAN, int MINW = 1, int RW = 0, bool DYN = false>
 hipError_t prepare_fused() {
     const size_t lds = sizeof(FusedTile<T, TX, TY>);
-    hipError_t e = hipFuncSetAttribute((const void*)k_fused<T, Pol, TX, TY, NT, 0, KAHAN, MINW>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_fused<T, Pol, TX, TY, NT, 0, KAHAN, MINW, RW, DYN>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_fused<T, Pol, TX, TY, NT, 1, KAHAN, MINW>,
+    return hipFuncSetAttribute((const void*)k_fused<T, Pol, TX, TY, NT, 1, KAHAN, MINW, RW, DYN>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 

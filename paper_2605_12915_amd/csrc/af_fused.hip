@@ -24,19 +24,23 @@
 
 namespace af {
 
-// 26x12 cells, 512 threads (156 KB of LDS, one workgroup per CU).  The heavy phases
-// run in whole rounds of 512 threads: phase 2 has 29x15 = 435 node-cells (one round,
-// as the 35x11 of a 32x8 tile, but for 312 owned cells instead of 256) and phase 3
-// 1013 targets (two rounds, 99% filled).  15% faster than 32x8; 28x12 (three phase-3
-// rounds), 24x13, 22x14 and 24x12 measured 1-12% slower than 26x12.
-constexpr int kTX = 26, kTY = 12, kNT = 512;
+// 31x10 cells, 512 threads (154 KB of LDS, one workgroup per CU).  Row stride of the
+// staged arrays 36 words; phase 2 has 34x13 = 442 node-cells (one round) and phase 3
+// places every target family in rows of 32 lanes: 32x11 V, 32x10 Ev and 31(+1)x11 Eh
+// targets fill exactly two rounds of 512, and a half-wavefront (the lanes the LDS
+// serves together) always reads 16 consecutive words.  The family is a run-time value
+// in phase 3 (DYN), so the two wavefronts that hold targets of two families run one
+// instruction stream.  Measured at 2048^2 against the earlier 26x12 tile with tight
+// item rows and the family as a template constant (1.030 ms): the run-time family
+// alone 0.968 ms, the 31x10 rows alone 1.011 ms, both 0.963 ms.
+constexpr int kTX = 31, kTY = 10, kNT = 512, kRW = 32;
 
 hipError_t launch_step_fused_f64(const StepArgs& a) {
     PolAbs<double> pol{a.gamma, 1.0 / (a.gamma - 1.0)};
-    return launch_fused<double, PolAbs<double>, kTX, kTY, kNT, false>(a, pol);
+    return launch_fused<double, PolAbs<double>, kTX, kTY, kNT, false, 1, kRW, true>(a, pol);
 }
 
-hipError_t prepare_fused_f64() { return prepare_fused<double, PolAbs<double>, kTX, kTY, kNT, false>(); }
+hipError_t prepare_fused_f64() { return prepare_fused<double, PolAbs<double>, kTX, kTY, kNT, false, 1, kRW, true>(); }
 
 size_t fused_lds_bytes() { return sizeof(FusedTile<double, kTX, kTY>); }
 

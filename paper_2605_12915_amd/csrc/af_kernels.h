@@ -83,6 +83,12 @@ template <> struct FamOffset<F_V> { static constexpr double ox = 0.0, oy = 0.0; 
 template <> struct FamOffset<F_EV> { static constexpr double ox = 0.0, oy = 0.5; };
 template <> struct FamOffset<F_EH> { static constexpr double ox = 0.5, oy = 0.0; };
 
+// The same offsets for a target family known only at run time (cell units).
+template <class T>
+AF_HD T fam_ox(int fam) { return fam == F_EH ? T(0.5) : T(0); }
+template <class T>
+AF_HD T fam_oy(int fam) { return fam == F_EV ? T(0.5) : T(0); }
+
 // Locate an offset (cell units, relative to the target's own cell) in its cell:
 // integer shift and local coordinate in [-1, 1].  A displacement of one cell or
 // more (or NaN) raises SB_FOOT and is replaced by the node itself, which keeps
@@ -96,12 +102,15 @@ AF_HD void locate(T off, T o, int& cell, T& xi, unsigned& st) {
 }
 
 // Transported (SCHEME 0, eq. transported-update) or additive (SCHEME 1,
-// eq. barsukow-additive) point update of target FAM at (i, j) for duration
-// tau = lam h (Sec. 6.1 steps 3-4).
-template <int FAM, int SCHEME, class T, class A, class D, class Pol>
-AF_HD Prim<T> point_update(const A& acc, const D& dinc, int i, int j, const Pol& pol, T lam, unsigned& st) {
-    const T ox = T(FamOffset<FAM>::ox), oy = T(FamOffset<FAM>::oy);
-    Prim<T> WP = acc.node(FAM, i, j);
+// eq. barsukow-additive) point update of the target of family fam (F_V, F_EV or
+// F_EH) at (i, j) for duration tau = lam h (Sec. 6.1 steps 3-4).  The family may be
+// a run-time value (lanes of one wavefront then share one instruction stream) or a
+// constant (point_update<FAM, ...>).
+template <int SCHEME, class T, class A, class D, class Pol>
+AF_HD Prim<T> point_update_f(const A& acc, const D& dinc, int fam, int i, int j, const Pol& pol, T lam,
+                             unsigned& st) {
+    const T ox = fam_ox<T>(fam), oy = fam_oy<T>(fam);
+    Prim<T> WP = acc.node(fam, i, j);
     int cx, cy;
     T xi, eta, xm, xp, ym, yp;
     // first Picard step: at a node the reconstruction equals the node value
@@ -152,12 +161,17 @@ AF_HD Prim<T> point_update(const A& acc, const D& dinc, int i, int j, const Pol&
         }
         rho_over_c2 = pol.rho(Wf.r) / (pol.gamma * pol.pr(Wf.p));    // 1 / c^2 at the foot
     } else {
-        du = dinc.inc(FAM, i, j, 0);
-        dv = dinc.inc(FAM, i, j, 1);
-        dp = dinc.inc(FAM, i, j, 2);
+        du = dinc.inc(fam, i, j, 0);
+        dv = dinc.inc(fam, i, j, 1);
+        dp = dinc.inc(fam, i, j, 2);
         rho_over_c2 = pol.rho(WP.r) / (pol.gamma * pol.pr(WP.p));    // frozen 1 / c^2 at P
     }
     return Prim<T>{Wf.r + dp * rho_over_c2, Wf.u + du, Wf.v + dv, Wf.p + dp};
+}
+
+template <int FAM, int SCHEME, class T, class A, class D, class Pol>
+AF_HD Prim<T> point_update(const A& acc, const D& dinc, int i, int j, const Pol& pol, T lam, unsigned& st) {
+    return point_update_f<SCHEME>(acc, dinc, FAM, i, j, pol, lam, st);
 }
 
 // Both durations of one target at once.  The two Picard stages of both durations
@@ -165,11 +179,11 @@ AF_HD Prim<T> point_update(const A& acc, const D& dinc, int i, int j, const Pol&
 // nine nodes and both increment sets are gathered once and every stage is checked
 // to stay in it.  Lanes whose feet leave it take the general path above, which
 // performs the same arithmetic (so the results do not depend on the path).
-template <int FAM, int SCHEME, class T, class A, class D, class Pol>
-AF_HD void point_update_pair(const A& acc, const D& d0, const D& d1, int i, int j, const Pol& pol, T lam0, T lam1,
-                             unsigned& st, Prim<T>& wh, Prim<T>& w1) {
-    const T ox = T(FamOffset<FAM>::ox), oy = T(FamOffset<FAM>::oy);
-    const Prim<T> WP = acc.node(FAM, i, j);
+template <int SCHEME, class T, class A, class D, class Pol>
+AF_HD void point_update_pair_f(const A& acc, const D& d0, const D& d1, int fam, int i, int j, const Pol& pol,
+                               T lam0, T lam1, unsigned& st, Prim<T>& wh, Prim<T>& w1) {
+    const T ox = fam_ox<T>(fam), oy = fam_oy<T>(fam);
+    const Prim<T> WP = acc.node(fam, i, j);
     // candidate cell from the longer first-stage displacement
     const T uP = pol.vu(WP.u), vP = pol.vv(WP.v);
     const T ex = ox - lam1 * uP, ey = oy - lam1 * vP;
@@ -231,9 +245,9 @@ AF_HD void point_update_pair(const A& acc, const D& d0, const D& d1, int i, int 
                 rho_over_c2 = pol.rho(Wf.r) / (pol.gamma * pol.pr(Wf.p));
             } else {
                 const D& dd = t ? d1 : d0;
-                du = dd.inc(FAM, i, j, 0);
-                dv = dd.inc(FAM, i, j, 1);
-                dp = dd.inc(FAM, i, j, 2);
+                du = dd.inc(fam, i, j, 0);
+                dv = dd.inc(fam, i, j, 1);
+                dp = dd.inc(fam, i, j, 2);
                 rho_over_c2 = pol.rho(WP.r) / (pol.gamma * pol.pr(WP.p));
             }
             wr[t] = Prim<T>{Wf.r + dp * rho_over_c2, Wf.u + du, Wf.v + dv, Wf.p + dp};
@@ -243,9 +257,15 @@ AF_HD void point_update_pair(const A& acc, const D& d0, const D& d1, int i, int 
         wh = wr[0];
         w1 = wr[1];
     } else {
-        wh = point_update<FAM, SCHEME>(acc, d0, i, j, pol, lam0, st);
-        w1 = point_update<FAM, SCHEME>(acc, d1, i, j, pol, lam1, st);
+        wh = point_update_f<SCHEME>(acc, d0, fam, i, j, pol, lam0, st);
+        w1 = point_update_f<SCHEME>(acc, d1, fam, i, j, pol, lam1, st);
     }
+}
+
+template <int FAM, int SCHEME, class T, class A, class D, class Pol>
+AF_HD void point_update_pair(const A& acc, const D& d0, const D& d1, int i, int j, const Pol& pol, T lam0, T lam1,
+                             unsigned& st, Prim<T>& wh, Prim<T>& w1) {
+    point_update_pair_f<SCHEME>(acc, d0, d1, FAM, i, j, pol, lam0, lam1, st, wh, w1);
 }
 
 }  // namespace af

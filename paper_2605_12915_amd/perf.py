@@ -47,8 +47,8 @@ _ADJ = ["csrc/af_adjoint.hip", "csrc/af_adjoint.h", "csrc/af_kernels.h", "csrc/a
 # the three kernels of one adjoint step (TAI point update)
 ADJOINT_KERNELS = ["af::k_adj_fwd", "af::k_adj_points<0>", "af::k_adj_incr"]
 KERNEL_SOURCES = {
-    "af::k_fused<double, af::PolAbs<double>, 26, 12, 512, 0, false, 1>": ["csrc/af_fused.hip"] + _STEP,
-    "af::k_fused<float, af::PolPert<float>, 24, 13, 512, 0, true, 4>": ["csrc/af_fused_f32.hip"] + _STEP,
+    "af::k_fused<double, af::PolAbs<double>, 31, 10, 512, 0, false, 1, 32, true>": ["csrc/af_fused.hip"] + _STEP,
+    "af::k_fused<float, af::PolPert<float>, 24, 13, 512, 0, true, 4, 0, false>": ["csrc/af_fused_f32.hip"] + _STEP,
     "af::k_fused_batch_direct<24, 13, 512, 4, 0>": ["csrc/af_batch.hip", "csrc/af_batch.h"] + _STEP,
     **{k: _ADJ for k in ADJOINT_KERNELS},
 }
