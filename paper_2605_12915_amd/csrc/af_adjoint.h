@@ -68,8 +68,15 @@ AF_HD void flux_y_T(const Prim<T>& w, T gamma, const T nu[4], T g[4]) {
 // of the new point value itself, for the full step).  The contributions to the
 // target's own node (through the first foot position) are added to gself, those to
 // the nodes of the two foot cells go to the window, one base offset per cell.
-template <int FAM, int SCHEME, class T, class S_, class O_>
-AF_HD void point_update_adj(const S_& S, const O_& O, int t, int i, int j, const Prim<T>& WP, T gamma, T lam,
+//
+// The two Picard stages normally lie in one foot cell; then each node's contribution
+// through the first stage's u1 = Q2(u) is added to its second-stage contribution
+// before a single scatter.  MODE 0 does that and returns true for a target whose
+// stages lie in different cells, whose first-stage contributions it leaves out; MODE 1
+// recomputes such a target and scatters only those (the caller runs it for the rare
+// wavefronts that need it, so the common path keeps one scatter per node and plane).
+template <int FAM, int SCHEME, int MODE, class T, class S_, class O_>
+AF_HD bool point_update_adj(const S_& S, const O_& O, int t, int i, int j, const Prim<T>& WP, T gamma, T lam,
                             const T nuF[4], const T nuG[4], T ws, const T* extra, T gself[4]) {
     const T ox = T(FamOffset<FAM>::ox), oy = T(FamOffset<FAM>::oy);
     constexpr int RX = O_::kRX;
@@ -182,21 +189,6 @@ AF_HD void point_update_adj(const S_& S, const O_& O, int t, int i, int j, const
 #pragma unroll
         for (int q = 0; q < 3; ++q) O.addb(16 + t * 12 + FAM * 3 + q, wbP, 0, lDf[q]);
     }
-    // Q2 values at the foot -> nodes of the foot cell
-    {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const T w = w2[a][b];
-                const int f = fam_of(a, b), off = (b == 2 ? RX : 0) + (a == 2 ? 1 : 0);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) O.addb(win_plane(f) + q, wb2, off, w * lWf[q]);
-                if constexpr (SCHEME == 0)
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) O.addb(16 + t * 12 + f * 3 + q, wb2, off, w * lDf[q]);
-            }
-    }
     // foot position: xi2 = 2 (off - floor(off)) - 1, off = ox - lam u1
     T lxi2 = T(0), leta2 = T(0);
 #pragma unroll
@@ -205,28 +197,53 @@ AF_HD void point_update_adj(const S_& S, const O_& O, int t, int i, int j, const
 #pragma unroll
         for (int q = 0; q < 3; ++q) { lxi2 += lDf[q] * dDx[q]; leta2 += lDf[q] * dDy[q]; }
     const T lu1 = T(-2) * lam * lxi2, lv1 = T(-2) * lam * leta2;
-    // first stage: u1 = Q2(u) at (xi1, eta1)
-    {
+    // Q2 values at the foot -> nodes of the foot cell, and the first stage's
+    // u1 = Q2(u) at (xi1, eta1): lu1, lv1 -> u, v of the first foot cell's nodes.  When
+    // both stages lie in one cell (the usual case) each node's two contributions are
+    // added before one scatter.
+    const bool same = wb1 == wb2;
+    if constexpr (MODE == 1) {
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                const T w = w1[a][b];
+                const T v = w1[a][b];
                 const int f = fam_of(a, b), off = (b == 2 ? RX : 0) + (a == 2 ? 1 : 0);
-                O.addb(win_plane(f) + 1, wb1, off, w * lu1);
-                O.addb(win_plane(f) + 2, wb1, off, w * lv1);
+                O.addb(win_plane(f) + 1, wb1, off, v * lu1);
+                O.addb(win_plane(f) + 2, wb1, off, v * lv1);
             }
+        return false;
     }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const T w = w2[a][b], v = w1[a][b];
+            const int f = fam_of(a, b), off = (b == 2 ? RX : 0) + (a == 2 ? 1 : 0);
+            O.addb(win_plane(f), wb2, off, w * lWf[0]);
+            O.addb(win_plane(f) + 1, wb2, off, w * lWf[1] + (same ? v * lu1 : T(0)));
+            O.addb(win_plane(f) + 2, wb2, off, w * lWf[2] + (same ? v * lv1 : T(0)));
+            O.addb(win_plane(f) + 3, wb2, off, w * lWf[3]);
+            if constexpr (SCHEME == 0)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) O.addb(16 + t * 12 + f * 3 + q, wb2, off, w * lDf[q]);
+        }
     const T lxi1 = lu1 * du1x + lv1 * dv1x, leta1 = lu1 * du1y + lv1 * dv1y;
     gself[1] += T(-2) * lam * lxi1;
     gself[2] += T(-2) * lam * leta1;
+    return !same;
 }
 
 // Reverse sweep of one target (family FAM of node-cell (i, j)): the adjoints of the
 // edge fluxes it feeds, from the averages' cotangents, then of its three time levels
 // (w^n directly, w^{n+1/2} and w^{n+1} through the transposed point update).
-template <int FAM, int SCHEME, class T, class S_, class CT, class O_>
-AF_HD void point_adj_target(const S_& S, const CT& cot1, const O_& O, int i, int j, T gamma, T lam0, T lam1) {
+// MODE 0 returns a bit per duration (1: tau = dt/2, 2: tau = dt) whose Picard stages
+// left one cell; MODE 1, given those bits, scatters the first-stage contributions that
+// MODE 0 left out (everything it needs is reloaded, so that the common path does not
+// keep it live).
+template <int FAM, int SCHEME, int MODE, class T, class S_, class CT, class O_>
+AF_HD unsigned point_adj_target(const S_& S, const CT& cot1, const O_& O, int i, int j, T gamma, T lam0, T lam1,
+                                unsigned fix = 0) {
     // cotangents of the time-integrated edge fluxes at this node: F at V and Ev, G at
     // V and Eh; spatial Simpson weights 1/6 (V, two edges each) and 4/6 (edge midpoints)
     T nuF[4] = {T(0), T(0), T(0), T(0)}, nuG[4] = {T(0), T(0), T(0), T(0)};
@@ -247,11 +264,21 @@ AF_HD void point_adj_target(const S_& S, const CT& cot1, const O_& O, int i, int
             nuG[k] = muG_ij * T(4.0 / 6.0);
         }
     }
-    // time level n (time-Simpson weight 1/6): the node itself
     const int wb = O.base(i, j);
     const int pl = win_plane(FAM);
     const Prim<T> w0{S.at(pl, wb, 0), S.at(pl + 1, wb, 0), S.at(pl + 2, wb, 0), S.at(pl + 3, wb, 0)};
     T g[4] = {T(0), T(0), T(0), T(0)};
+    if constexpr (MODE == 1) {
+        if (fix & 1u)
+            point_update_adj<FAM, SCHEME, 1>(S, O, 0, i, j, w0, gamma, lam0, nuF, nuG, T(4.0 / 6.0), (const T*)nullptr, g);
+        if (fix & 2u) {
+            const T extra[4] = {cot1.get(4 + 4 * FAM, i, j), cot1.get(5 + 4 * FAM, i, j), cot1.get(6 + 4 * FAM, i, j),
+                                cot1.get(7 + 4 * FAM, i, j)};
+            point_update_adj<FAM, SCHEME, 1>(S, O, 1, i, j, w0, gamma, lam1, nuF, nuG, T(1.0 / 6.0), extra, g);
+        }
+        return 0u;
+    }
+    // time level n (time-Simpson weight 1/6): the node itself
     {
         T nu[4];
         if constexpr (FAM != F_EH) {
@@ -266,12 +293,17 @@ AF_HD void point_adj_target(const S_& S, const CT& cot1, const O_& O, int i, int
         }
     }
     // n + 1/2 (weight 4/6) and n + 1 (weight 1/6; also an output of the step)
-    point_update_adj<FAM, SCHEME>(S, O, 0, i, j, w0, gamma, lam0, nuF, nuG, T(4.0 / 6.0), (const T*)nullptr, g);
+    unsigned out = 0u;
+    if (point_update_adj<FAM, SCHEME, 0>(S, O, 0, i, j, w0, gamma, lam0, nuF, nuG, T(4.0 / 6.0), (const T*)nullptr,
+                                         g))
+        out |= 1u;
     const T extra[4] = {cot1.get(4 + 4 * FAM, i, j), cot1.get(5 + 4 * FAM, i, j), cot1.get(6 + 4 * FAM, i, j),
                         cot1.get(7 + 4 * FAM, i, j)};
-    point_update_adj<FAM, SCHEME>(S, O, 1, i, j, w0, gamma, lam1, nuF, nuG, T(1.0 / 6.0), extra, g);
+    if (point_update_adj<FAM, SCHEME, 0>(S, O, 1, i, j, w0, gamma, lam1, nuF, nuG, T(1.0 / 6.0), extra, g))
+        out |= 2u;
 #pragma unroll
     for (int q = 0; q < 4; ++q) O.addb(pl + q, wb, 0, g[q]);
+    return out;
 }
 
 // Transposed 1-D Lagrange-to-monomial transform (see mono1): (lc0, lc1, lc2) -> (lf0, lf1, lf2).

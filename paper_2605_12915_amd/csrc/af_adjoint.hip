@@ -283,27 +283,30 @@ __global__ void __launch_bounds__(kFNT, 2) k_adj_fwd(StatePtrs<double> prim, dou
 // 8x8 blocks: the staged state and the window take 77 KB, so two blocks share a CU and
 // one's staging overlaps the other's work (2% faster than 16x8 at one block per CU,
 // despite the larger window overlap, 1.89x against 1.63x).
-constexpr int kPBX = 8, kPBY = 8, kPNT = 3 * kPBX * kPBY;
-constexpr int kPRX = kPBX + 3, kPRY = kPBY + 3, kPWin = kPRX * kPRY;
-using PointWin = LdsWin<40, kPRX, kPRY>;
-using PointStage = StageWin<kPRX, kPRY>;
-constexpr size_t kPointLds = sizeof(double) * 2 * 40 * kPWin;   // staged state + accumulators
-static_assert(kPWin <= kPNT, "one staging round");
+template <int BX, int BY>
+struct PointBlock {
+    static constexpr int NT = 3 * BX * BY, RX = BX + 3, RY = BY + 3, WIN = RX * RY;
+    static constexpr size_t LDS = sizeof(double) * 2 * 40 * WIN;   // staged state + accumulators
+    static_assert(WIN <= NT, "one staging round");
+    static_assert((BX * BY) % 64 == 0, "each wavefront holds one target family");
+};
 
-// (registers bounded for 2 waves per SIMD: the workgroup alone would let the compiler
-// take accumulation registers too, and the RB instantiation did, at one wave per SIMD)
-template <int SCHEME>
-__global__ void __launch_bounds__(kPNT, 2) k_adj_points(StatePtrs<double> prim, const double* C, const double* Dfwd,
-                                                     StatePtrs<double> cot1, PlaneList G, int nx, int ny,
-                                                     double gamma, double lam0, double lam1) {
+// (registers bounded for MINB blocks per CU at 2 waves per SIMD: the workgroup alone
+// would let the compiler take accumulation registers too, and the RB instantiation did,
+// at one wave per SIMD)
+template <int SCHEME, int BX, int BY, int MINB>
+__global__ void __launch_bounds__(3 * BX * BY, MINB)
+    k_adj_points(StatePtrs<double> prim, const double* C, const double* Dfwd, StatePtrs<double> cot1, PlaneList G,
+                 int nx, int ny, double gamma, double lam0, double lam1) {
+    using B = PointBlock<BX, BY>;
     extern __shared__ __align__(16) unsigned char smem[];
     double* stage = reinterpret_cast<double*>(smem);   // [40][RY][RX]
-    const int i0 = blockIdx.x * kPBX, j0 = blockIdx.y * kPBY;
-    const PointWin O{stage + 40 * kPWin, i0 - 1, j0 - 1};
+    const int i0 = blockIdx.x * BX, j0 = blockIdx.y * BY;
+    const LdsWin<40, B::RX, B::RY> O{stage + 40 * B::WIN, i0 - 1, j0 - 1};
     O.zero();
-    if (threadIdx.x < kPWin) {
+    if (threadIdx.x < B::WIN) {
         const int e = threadIdx.x;
-        const int i = wrap_any(i0 - 1 + e % kPRX, nx), j = wrap_any(j0 - 1 + e / kPRX, ny);
+        const int i = wrap_any(i0 - 1 + e % B::RX, nx), j = wrap_any(j0 - 1 + e / B::RX, ny);
         const size_t N = (size_t)nx * ny, k = (size_t)j * nx + i;
         double v[40];
 #pragma unroll
@@ -313,20 +316,46 @@ __global__ void __launch_bounds__(kPNT, 2) k_adj_points(StatePtrs<double> prim, 
 #pragma unroll
         for (int q = 0; q < 24; ++q) v[16 + q] = Dfwd[q * N + k];
 #pragma unroll
-        for (int pl = 0; pl < 40; ++pl) stage[pl * kPWin + e] = v[pl];
+        for (int pl = 0; pl < 40; ++pl) stage[pl * B::WIN + e] = v[pl];
     }
     __syncthreads();
-    const PointStage S{stage, i0 - 1, j0 - 1};
-    const int cell = (int)threadIdx.x % (kPBX * kPBY), fam = (int)threadIdx.x / (kPBX * kPBY);   // wave-uniform
-    const int i = i0 + cell % kPBX, j = j0 + cell / kPBX;
+    const StageWin<B::RX, B::RY> S{stage, i0 - 1, j0 - 1};
+    const int cell = (int)threadIdx.x % (BX * BY), fam = (int)threadIdx.x / (BX * BY);   // wave-uniform
+    const int i = i0 + cell % BX, j = j0 + cell / BX;
     if (i < nx && j < ny) {
         const CotAcc C1{cot1, nx, ny};
-        if (fam == F_V) point_adj_target<F_V, SCHEME>(S, C1, O, i, j, gamma, lam0, lam1);
-        else if (fam == F_EV) point_adj_target<F_EV, SCHEME>(S, C1, O, i, j, gamma, lam0, lam1);
-        else point_adj_target<F_EH, SCHEME>(S, C1, O, i, j, gamma, lam0, lam1);
+        unsigned fix;
+        if (fam == F_V) fix = point_adj_target<F_V, SCHEME, 0>(S, C1, O, i, j, gamma, lam0, lam1);
+        else if (fam == F_EV) fix = point_adj_target<F_EV, SCHEME, 0>(S, C1, O, i, j, gamma, lam0, lam1);
+        else fix = point_adj_target<F_EH, SCHEME, 0>(S, C1, O, i, j, gamma, lam0, lam1);
+        // targets whose Picard stages left one cell (rare): their first-stage share
+        if (__any(fix != 0u)) {
+            if (fam == F_V) point_adj_target<F_V, SCHEME, 1>(S, C1, O, i, j, gamma, lam0, lam1, fix);
+            else if (fam == F_EV) point_adj_target<F_EV, SCHEME, 1>(S, C1, O, i, j, gamma, lam0, lam1, fix);
+            else point_adj_target<F_EH, SCHEME, 1>(S, C1, O, i, j, gamma, lam0, lam1, fix);
+        }
     }
     __syncthreads();
     flush_window(O, G, nx, ny);
+}
+
+template <int SCHEME, int BX, int BY, int MINB>
+void launch_points(const StepArgs& a, StatePtrs<double> prim, const double* C, const double* Dfwd,
+                   StatePtrs<double> cot1, const PlaneList& L, double lam0, double lam1) {
+    using B = PointBlock<BX, BY>;
+    dim3 grd((a.nx + BX - 1) / BX, (a.ny + BY - 1) / BY);
+    hipLaunchKernelGGL((k_adj_points<SCHEME, BX, BY, MINB>), grd, dim3(B::NT), B::LDS, a.stream, prim, C, Dfwd, cot1,
+                       L, a.nx, a.ny, a.gamma, lam0, lam1);
+}
+
+template <int BX, int BY, int MINB>
+hipError_t prepare_points() {
+    using B = PointBlock<BX, BY>;
+    hipError_t e = hipFuncSetAttribute((const void*)k_adj_points<0, BX, BY, MINB>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)B::LDS);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_adj_points<1, BX, BY, MINB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)B::LDS);
 }
 
 // Transposed node increments and centre recovery for a BX x BY block of node-cells.
@@ -417,16 +446,10 @@ hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1_[16], vo
                            lam0, lam1, a.status);
     }
     if (a.ev_begin) (void)hipEventRecord(a.ev_begin, a.stream);
-    {
-        const size_t lds = kPointLds;   // allowed by prepare_adjoint_f64
-        dim3 grd((a.nx + kPBX - 1) / kPBX, (a.ny + kPBY - 1) / kPBY);
-        if (a.scheme == 0)
-            hipLaunchKernelGGL(k_adj_points<0>, grd, dim3(kPNT), lds, a.stream, prim, C, Dfwd, cot1, L, a.nx, a.ny,
-                               a.gamma, lam0, lam1);
-        else
-            hipLaunchKernelGGL(k_adj_points<1>, grd, dim3(kPNT), lds, a.stream, prim, C, Dfwd, cot1, L, a.nx, a.ny,
-                               a.gamma, lam0, lam1);
-    }
+    // point kernel: 8x8-cell blocks, two per CU (16x8 blocks at one per CU, whose
+    // half-wavefronts read rows of 16 consecutive words, measured 3% slower)
+    if (a.scheme == 0) launch_points<0, 8, 8, 2>(a, prim, C, Dfwd, cot1, L, lam0, lam1);
+    else launch_points<1, 8, 8, 2>(a, prim, C, Dfwd, cot1, L, lam0, lam1);
     {
         dim3 grd((a.nx + kIBX - 1) / kIBX, (a.ny + kIBY - 1) / kIBY);
         hipLaunchKernelGGL(k_adj_incr, grd, dim3(kIBX * kIBY), 0, a.stream, prim, C, lD, lC, Li, a.nx, a.ny, a.gamma,
@@ -436,13 +459,7 @@ hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1_[16], vo
     return hipGetLastError();
 }
 
-hipError_t prepare_adjoint_f64() {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_adj_points<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)kPointLds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_adj_points<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)kPointLds);
-}
+hipError_t prepare_adjoint_f64() { return prepare_points<8, 8, 2>(); }
 
 size_t scratch_bytes_adjoint_f64(int nx, int ny) { return (size_t)nx * ny * (4 + 24 + 4 + 24) * sizeof(double); }
 

@@ -187,9 +187,10 @@ int main() {
     node_increments<F_C>(A, 2, 2, pol, lam0, lam1, d, st);
     const long adj_fwd = total() - a0;
     long a1 = total();
-    point_adj_target<F_V, 0>(S, cot, O, 2, 2, gamma, lam0, lam1);
-    point_adj_target<F_EV, 0>(S, cot, O, 2, 2, gamma, lam0, lam1);
-    point_adj_target<F_EH, 0>(S, cot, O, 2, 2, gamma, lam0, lam1);
+    unsigned fix = point_adj_target<F_V, 0, 0>(S, cot, O, 2, 2, gamma, lam0, lam1);
+    fix |= point_adj_target<F_EV, 0, 0>(S, cot, O, 2, 2, gamma, lam0, lam1);
+    fix |= point_adj_target<F_EH, 0, 0>(S, cot, O, 2, 2, gamma, lam0, lam1);
+    if (fix) std::fprintf(stderr, "warning: a counted target's Picard stages left one cell\n");
     const long adj_points = total() - a1;
     a1 = total();
     incr_adj<F_V>(A, lD, O, 2, 2, gamma, lam0, lam1);

@@ -45,7 +45,7 @@ _STEP = ["csrc/af_fused.h", "csrc/af_kernels.h", "csrc/af_device.h", "csrc/af_bl
 _ADJ = ["csrc/af_adjoint.hip", "csrc/af_adjoint.h", "csrc/af_kernels.h", "csrc/af_device.h", "csrc/af_blocks.h",
         "csrc/af_internal.h", "build.py"]
 # the three kernels of one adjoint step (TAI point update)
-ADJOINT_KERNELS = ["af::k_adj_fwd", "af::k_adj_points<0>", "af::k_adj_incr"]
+ADJOINT_KERNELS = ["af::k_adj_fwd", "af::k_adj_points<0, 8, 8, 2>", "af::k_adj_incr"]
 KERNEL_SOURCES = {
     "af::k_fused<double, af::PolAbs<double>, 31, 10, 512, 0, false, 1, 32, true>": ["csrc/af_fused.hip"] + _STEP,
     "af::k_fused<float, af::PolPert<float>, 24, 13, 512, 0, true, 4, 0, false>": ["csrc/af_fused_f32.hip"] + _STEP,
