@@ -112,6 +112,70 @@ def test_rollout_gradient_vs_fd(torch_dev):
         assert rel < 1e-6
 
 
+def test_config4_gradient_vs_fd_512(torch_dev):
+    """The differentiation workload at full size: 512^2 Gaussian acoustic pulse with
+    seeded centre jitter, 200 steps at CFL 0.4 with checkpoints every 20, gradient of
+    the acoustic energy in the annulus 0.10 <= r <= 0.20 (cell-average primitives)
+    with respect to the four initial density planes, against central differences in 8
+    random directions of that subspace.  Bar: relative error <= 1e-6 per direction at
+    the step eps = u^(1/3) max|rho| that balances truncation against rounding (u the
+    unit roundoff); at eps = 1e-6 max|rho| the rounding of the 200-step functional
+    dominates in directions with small derivatives, so there the bar is 1e-6 of
+    |grad| |d| (the normwise form)."""
+    torch, dev = torch_dev
+    from paper_2605_12915_amd.autodiff import rollout
+    from paper_2605_12915_amd.stepper import Stepper
+    n, steps, every = 512, 200, 20
+    P = I.acoustic_pulse_adjoint(n)
+    s0 = P.state()
+    dt = P.dt_for_cfl(0.4)
+    g = P.gamma
+    st = Stepper(P.nx, P.ny, P.h, g, device=dev)
+    x0 = torch.from_numpy(s0).to(dev)
+    c = (np.arange(n) + 0.5) * P.h
+    X, Y = np.meshgrid(c, c)
+    r = np.sqrt((X - 0.5) ** 2 + (Y - 0.5) ** 2)
+    mask = torch.from_numpy(((r >= 0.10) & (r <= 0.20)).astype(np.float64)).to(dev)
+    rho0, p0 = P.bg[0], P.bg[3]
+    c0sq = g * p0 / rho0
+
+    def J(x):
+        U = x[:4]
+        rho = U[0]
+        u, v = U[1] / rho, U[2] / rho
+        p = (g - 1.0) * (U[3] - 0.5 * rho * (u * u + v * v))
+        e = (p - p0) ** 2 / (2.0 * rho0 * c0sq) + 0.5 * rho0 * (u * u + v * v)
+        return P.h * P.h * torch.sum(mask * e)
+
+    def J_plain(x):
+        z = x.clone()
+        st.step(z, dt, steps)
+        return float(J(z))
+
+    xg = x0.clone().requires_grad_(True)
+    J(rollout(xg, st, dt, steps, every)).backward()
+    G = xg.grad.detach()
+    rho_planes = [0, 4, 8, 12]
+    scale = float(x0[rho_planes].abs().max())
+    gnorm = float(G[rho_planes].norm())
+    rng = np.random.default_rng(8)
+    eps_opt, eps6 = np.cbrt(np.finfo(np.float64).eps) * scale, 1e-6 * scale
+    with torch.no_grad():
+        for k in range(8):
+            d = torch.zeros_like(x0)
+            for pl in rho_planes:
+                d[pl] = torch.from_numpy(rng.normal(size=s0.shape[1:])).to(dev)
+            ad = float(torch.sum(G * d))
+            fd = (J_plain(x0 + eps_opt * d) - J_plain(x0 - eps_opt * d)) / (2.0 * eps_opt)
+            fd6 = (J_plain(x0 + eps6 * d) - J_plain(x0 - eps6 * d)) / (2.0 * eps6)
+            rel = abs(fd - ad) / abs(ad)
+            nrm6 = abs(fd6 - ad) / (gnorm * float(d.norm()))
+            print(f"direction {k}: ad {ad:.12e} rel err {rel:.2e} (eps {eps_opt:.1e}), "
+                  f"{abs(fd6 - ad) / abs(ad):.2e} / normwise {nrm6:.2e} (eps {eps6:.1e})", flush=True)
+            assert rel <= 1e-6
+            assert nrm6 <= 1e-6
+
+
 @pytest.mark.parametrize("scheme", ["tai", "rb"])
 def test_rollout_gradient_vs_oracle_jvp(torch_dev, orc, scheme):
     """The checkpointed rollout's gradient (autograd through 30 steps, checkpoints every
