@@ -19,7 +19,8 @@ STATUS = {0: "ok", 1: "acoustic_cfl", 2: "foot", 3: "nonphysical"}
 def lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "liborc.so")
+        # AF_ORACLE_LIB selects another build of the same source (the sanitizer build)
+        path = os.environ.get("AF_ORACLE_LIB") or os.path.join(_HERE, "liborc.so")
         if not os.path.exists(path):
             from . import build
             build.build()

@@ -6,53 +6,9 @@
 
 #include "af_internal.h"
 #include "af_kernels.h"
+#include "af_tile.h"
 
 namespace af {
-
-// FP64: P, C and D share one row stride (PX), and phases 1 and 2 walk their items in
-// rows of that stride (the items past a region's width idle), so the lanes of a wave
-// read consecutive LDS words of every plane instead of colliding on banks where the
-// rows of the item grid and of the array wrap at different widths (2% faster).  The
-// FP32 instantiation keeps tight rows: its 128-register budget spills with the
-// strided loops.
-template <class T, int TX, int TY>
-struct FusedTile {
-    static constexpr int PX = TX + 5, PY = TY + 5;   // primitives: cells [-2, T+3)
-    static constexpr int CX = TX + 4, CY = TY + 4;   // centres:    cells [-2, T+2)
-    static constexpr int DX = TX + 3, DY = TY + 3;   // increments: node-cells [-1, T+2)
-    static constexpr int VX = TX + 1, VY = TY + 1;   // flux nodes: node-cells [0, T]
-    static constexpr bool kCommon = sizeof(T) == 8;
-    static constexpr int SC = kCommon ? PX : CX, SD = kCommon ? PX : DX;   // row strides of C, D
-    T P[12][PY][PX];
-    T C[4][CY][SC];
-    union {
-        T D[2][12][DY][SD];                          // [tau][fam*3 + var]
-        struct {
-            T FV[8][VY][VX];                         // V nodes: F~ (0..3), G~ (4..7)
-            T FE[4][TY][VX];                         // Ev nodes: F~
-            T GE[4][VY][TX];                         // Eh nodes: G~
-        } F;
-    };
-};
-
-template <class T, int TX, int TY>
-struct LdsAcc {
-    const FusedTile<T, TX, TY>* t;
-    __device__ __forceinline__ Prim<T> node(int fam, int x, int y) const {
-        if (fam == F_C) return {t->C[0][y + 2][x + 2], t->C[1][y + 2][x + 2], t->C[2][y + 2][x + 2], t->C[3][y + 2][x + 2]};
-        const int b = 4 * fam;
-        return {t->P[b][y + 2][x + 2], t->P[b + 1][y + 2][x + 2], t->P[b + 2][y + 2][x + 2], t->P[b + 3][y + 2][x + 2]};
-    }
-};
-
-template <class T, int TX, int TY>
-struct LdsInc {
-    const FusedTile<T, TX, TY>* t;
-    int tau;
-    __device__ __forceinline__ T inc(int fam, int x, int y, int var) const {
-        return t->D[tau][fam * 3 + var][y + 1][x + 1];
-    }
-};
 
 template <int B, class SP, class T>
 __device__ __forceinline__ void store_prim(const SP& o, size_t g, const Prim<T>& w) {
@@ -60,18 +16,6 @@ __device__ __forceinline__ void store_prim(const SP& o, size_t g, const Prim<T>&
     o.p[B + 1][g] = w.u;
     o.p[B + 2][g] = w.v;
     o.p[B + 3][g] = w.p;
-}
-
-__device__ __forceinline__ int wrap_any(int v, int n) {
-    v %= n;
-    return v < 0 ? v + n : v;
-}
-
-// Periodic index of the tile window: one conditional shift when the grid is at least
-// as large as the window (the usual case, decided per launch), else a modulo.
-__device__ __forceinline__ int wrap_win(int v, int n, bool one) {
-    if (one) return v < 0 ? v + n : (v >= n ? v - n : v);
-    return wrap_any(v, n);
 }
 
 // One tile: cells [i0, i0+TX) x [j0, j0+TY) of one grid.  Called by the single-grid
@@ -114,8 +58,8 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int e = r * NT + tid;
-            if (e < NP0) {
-                const int x = e % Tile::PX, y = e / Tile::PX;
+            int x, y;
+            if (Tile::stage_item(e, x, y)) {
                 const size_t g = (size_t)wrap_win(j0 + y - 2, ny, oney) * nx + wrap_win(i0 + x - 2, nx, onex);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) pv[r][k] = in.p[4 + k][g];
@@ -124,13 +68,15 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int e = r * NT + tid;
-            if (e < NP0)
+            int x, y;
+            if (Tile::stage_item(e, x, y))
 #pragma unroll
-                for (int k = 0; k < 12; ++k) L.P[k][e / Tile::PX][e % Tile::PX] = pv[r][k];
+                for (int k = 0; k < 12; ++k) L.P[k][y][x] = pv[r][k];
         }
     } else {
         for (int e = tid; e < Tile::PX * Tile::PY; e += NT) {
-            const int x = e % Tile::PX, y = e / Tile::PX;
+            int x, y;
+            Tile::stage_item(e, x, y);
             const size_t g = (size_t)wrap_win(j0 + y - 2, ny, oney) * nx + wrap_win(i0 + x - 2, nx, onex);
 #pragma unroll
             for (int k = 0; k < 12; ++k) L.P[k][y][x] = in.p[4 + k][g];
@@ -142,8 +88,8 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
     {
         LdsAcc<T, TX, TY> A{&L};
         for (int e = tid; e < Tile::SC * Tile::CY; e += NT) {
-            const int x = e % Tile::SC - 2, y = e / Tile::SC - 2;
-            if (x + 2 >= Tile::CX) continue;
+            int x, y;
+            if (!Tile::centre_item(e, x, y)) continue;
             const size_t g = (size_t)wrap_win(j0 + y, ny, oney) * nx + wrap_win(i0 + x, nx, onex);
             const T Ub[4] = {in.p[0][g], in.p[1][g], in.p[2][g], in.p[3][g]};
             Prim<T> w = pol.centre(Ub, A.node(F_V, x, y), A.node(F_V, x + 1, y), A.node(F_V, x, y + 1),
@@ -162,8 +108,8 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
     {
         LdsAcc<T, TX, TY> A{&L};
         for (int e = tid; e < Tile::SD * Tile::DY; e += NT) {
-            const int x = e % Tile::SD - 1, y = e / Tile::SD - 1;
-            if (x + 1 >= Tile::DX) continue;
+            int x, y;
+            if (!Tile::incr_item(e, x, y)) continue;
             T d[2][3];
             node_increments<F_V>(A, x, y, pol, lam0, lam1, d, st);
 #pragma unroll
@@ -193,19 +139,10 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
     __syncthreads();
 
     // ---- phase 3: point updates of targets in node-cells [0, T] ----------------------
-    // items: V targets (VX x VY), then Ev (VX x TY), then Eh (TX x VY), each family in
-    // rows of WV / WE / WH lanes (lanes past the family's row width idle)
-    constexpr int WV = RW ? RW : Tile::VX, WE = RW ? RW : Tile::VX, WH = RW ? RW : TX;
-    static_assert(WV >= Tile::VX && WH >= TX, "item rows hold a row of targets");
-    constexpr int NV_ = WV * Tile::VY, NE_ = WE * TY, NH_ = WH * Tile::VY;
-    constexpr int NITEMS = NV_ + NE_ + NH_;
+    using Pts = typename Tile::template Points<RW>;
+    static_assert(Pts::WV >= Tile::VX && Pts::WH >= TX, "item rows hold a row of targets");
+    constexpr int NITEMS = Pts::N;
     constexpr int ROUNDS = (NITEMS + NT - 1) / NT;
-    auto decode = [&](int e, int& fam, int& x, int& y) -> bool {
-        if (e < NV_) { fam = F_V; x = e % WV; y = e / WV; return x < Tile::VX; }
-        if (e < NV_ + NE_) { fam = F_EV; x = (e - NV_) % WE; y = (e - NV_) / WE; return x < Tile::VX; }
-        fam = F_EH; x = (e - NV_ - NE_) % WH; y = (e - NV_ - NE_) / WH;
-        return x < TX;
-    };
     T fres[ROUNDS][8];
     {
         LdsAcc<T, TX, TY> A{&L};
@@ -213,9 +150,8 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
 #pragma unroll
         for (int r = 0; r < ROUNDS; ++r) {
             const int e = r * NT + tid;
-            if (e >= NITEMS) continue;
             int fam, x, y;
-            if (!decode(e, fam, x, y)) continue;
+            if (!Pts::item(e, fam, x, y)) continue;
             Prim<T> w0, wh, w1;
             // new point values of owned nodes (plane indices kept static: a dynamic
             // index into the pointer set would put it in private memory)
@@ -266,8 +202,8 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
 #pragma unroll
         for (int r = 0; r < R4; ++r) {
             const int e = r * NT + tid;
-            const int x = e % TX, y = e / TX;
-            if (e < TX * TY && i0 + x < nx && j0 + y < ny) {
+            int x, y;
+            if (Tile::update_item(e, x, y) && i0 + x < nx && j0 + y < ny) {
                 const size_t g = (size_t)(j0 + y) * nx + (i0 + x);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) oldv[r][k] = in.p[k][g];
@@ -284,9 +220,8 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
         const int e = r * NT + tid;
-        if (e >= NITEMS) continue;
         int fam, x, y;
-        if (!decode(e, fam, x, y)) continue;
+        if (!Pts::item(e, fam, x, y)) continue;
         if (fam == F_V) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) L.F.FV[k][y][x] = fres[r][k];
@@ -313,8 +248,8 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
 #pragma unroll
         for (int r = 0; r < R4; ++r) {
             const int e = r * NT + tid;
-            if (e >= TX * TY) continue;
-            const int x = e % TX, y = e / TX;
+            int x, y;
+            if (!Tile::update_item(e, x, y)) continue;
             if (i0 + x >= nx || j0 + y >= ny) continue;
             const size_t g = (size_t)(j0 + y) * nx + (i0 + x);
 #pragma unroll
@@ -337,7 +272,8 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
         }
     } else {
         for (int e = tid; e < TX * TY; e += NT) {
-            const int x = e % TX, y = e / TX;
+            int x, y;
+            Tile::update_item(e, x, y);
             if (i0 + x >= nx || j0 + y >= ny) continue;
             const size_t g = (size_t)(j0 + y) * nx + (i0 + x);
 #pragma unroll
