@@ -182,7 +182,7 @@ af_status af_time_steps(af_ctx* ctx, const af_state* s, double dt, int32_t nstep
  * most 16 distinct nsteps are kept at a time).  The tile shape is chosen by an
  * autotuner on the first af_step_batch call: every compiled candidate is timed on a
  * copy of the batch's states and the fastest is kept (af_batch_info reports the
- * timings); the environment variable AF_BATCH_TILE=k (0 <= k < 14), read by
+ * timings); the environment variable AF_BATCH_TILE=k (0 <= k < 15), read by
  * af_init_batch, fixes candidate k instead.  With AF_BATCH_TUNE_CACHE=path (also read
  * by af_init_batch) the tuner first looks the batch up in that text file, keyed by
  * device architecture and compute units, candidate table, point update and the grids'
@@ -193,7 +193,8 @@ af_status af_time_steps(af_ctx* ctx, const af_state* s, double dt, int32_t nstep
  * in the persistent grid mode (k < 6: CUs x resident workgroups looping over the
  * work list), then in the direct mode (6 <= k < 12: one workgroup per work item),
  * and k = 12, 13: 32x8/512 and 24x13/512 direct with registers capped for two
- * workgroups per CU.  Each
+ * workgroups per CU, and k = 14: 31x10/512 direct, capped, with the point-update
+ * targets in rows of 32 lanes (the single-grid FP32 kernel's configuration).  Each
  * grid keeps its own Kahan compensation planes, tied to the trajectory as for AF_F32
  * contexts.  The library allocates one partner state and four compensation planes
  * per grid.  hip_stream is borrowed; replays run on an internal stream ordered after

@@ -317,7 +317,7 @@ std::string batch_tune_key(const af_ctx* c) {
     for (int k = 0; k < af::kNumBatchCfgs; ++k) {
         const af::BatchTileCfg t = af::kBatchCfgs[k];
         h = fnv1a(h, ((uint64_t)t.tx << 48) ^ ((uint64_t)t.ty << 32) ^ ((uint64_t)t.nt << 8) ^ (t.direct ? 4u : 0u) ^
-                         (uint64_t)t.minw);
+                         (uint64_t)t.minw ^ ((uint64_t)t.rw << 16));
     }
     for (const af::BatchInst& d : c->binst) h = fnv1a(h, ((uint64_t)(uint32_t)d.nx << 32) | (uint32_t)d.ny);
     char buf[160];
@@ -895,7 +895,7 @@ int32_t af_batch_info(af_ctx* c, char* buf, int32_t buflen) {
         const af::BatchTileCfg t = af::kBatchCfgs[c->tune_cfg];
         s += "[" + std::to_string(t.tx) + ", " + std::to_string(t.ty) + ", " + std::to_string(t.nt) + "]";
         s += std::string(", \"mode\": \"") + (t.direct ? "direct" : "persistent") + "\", \"min_waves\": " +
-             std::to_string(t.minw);
+             std::to_string(t.minw) + ", \"target_rows\": " + std::to_string(t.rw);
     } else {
         s += "null";
     }
@@ -905,8 +905,9 @@ int32_t af_batch_info(af_ctx* c, char* buf, int32_t buflen) {
         const af::BatchTileCfg t = af::kBatchCfgs[k];
         char tmp[200];
         std::snprintf(tmp, sizeof(tmp),
-                      "%s{\"tile\": [%d, %d, %d], \"mode\": \"%s\", \"min_waves\": %d, \"ms_per_step\": %.6f}",
-                      k ? ", " : "", t.tx, t.ty, t.nt, t.direct ? "direct" : "persistent", t.minw, c->tune_ms[k]);
+                      "%s{\"tile\": [%d, %d, %d], \"mode\": \"%s\", \"min_waves\": %d, \"target_rows\": %d, "
+                      "\"ms_per_step\": %.6f}",
+                      k ? ", " : "", t.tx, t.ty, t.nt, t.direct ? "direct" : "persistent", t.minw, t.rw, c->tune_ms[k]);
         s += tmp;
     }
     s += "]}";
@@ -923,13 +924,13 @@ const char* af_dominant_kernel(af_ctx* c) {
         c->kname = std::string(t.direct ? "af::k_fused_batch_direct<" : "af::k_fused_batch<") + std::to_string(t.tx) +
                    ", " + std::to_string(t.ty) + ", " + std::to_string(t.nt) +
                    (t.direct ? ", " + std::to_string(t.minw) : std::string()) + ", " +
-                   std::to_string(batch_scheme(c)) + ">";
+                   std::to_string(batch_scheme(c)) + (t.direct ? ", " + std::to_string(t.rw) : std::string()) + ">";
         return c->kname.c_str();
     }
     const bool rb = c && (c->cfg.flags & AF_SCHEME_RB);
     if (c && c->f32)
-        return rb ? "af::k_fused<float, af::PolPert<float>, 24, 13, 512, 1, true, 4, 0, false>"
-                  : "af::k_fused<float, af::PolPert<float>, 24, 13, 512, 0, true, 4, 0, false>";
+        return rb ? "af::k_fused<float, af::PolPert<float>, 31, 10, 512, 1, true, 4, 32, true>"
+                  : "af::k_fused<float, af::PolPert<float>, 31, 10, 512, 0, true, 4, 32, true>";
     if (c && c->variant == 1) return "af_step multi-kernel sequence";
     if (c && c->variant == 2) return rb ? "af::k_points_update<32, 8, 512, 1>" : "af::k_points_update<32, 8, 512, 0>";
     return rb ? "af::k_fused<double, af::PolAbs<double>, 31, 10, 512, 1, false, 1, 32, true>"

@@ -32,8 +32,10 @@ struct PlaneView {
     } p;
 };
 
-struct BatchTileCfg { int tx, ty, nt; bool direct; int minw; };
-constexpr int kNumBatchCfgs = 14;
+// rw: point-update targets in rows of rw lanes with the family a run-time value
+// (0: tight rows, family a template constant), as in the single-grid kernels
+struct BatchTileCfg { int tx, ty, nt; bool direct; int minw; int rw; };
+constexpr int kNumBatchCfgs = 15;
 extern const BatchTileCfg kBatchCfgs[kNumBatchCfgs];
 
 // scheme: 0 transported (TAI), 1 additive (RB) point update, for the whole batch

@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) k_
 // Direct grid mode: one workgroup per work item (the hardware dispatcher balances the
 // load), tile body inlined exactly as in the single-grid kernel.  Work items are
 // numbered XCD-aware: each XCD gets a contiguous run of the list.
-template <int TX, int TY, int NT, int MINW, int SCHEME>
+template <int TX, int TY, int NT, int MINW, int SCHEME, int RW = 0>
 __global__ void __launch_bounds__(NT, MINW) k_fused_batch_direct(const BatchInst* __restrict__ inst,
                                                            const int2* __restrict__ work, int nwork, int parity,
                                                            unsigned* status) {
@@ -75,8 +75,8 @@ __global__ void __launch_bounds__(NT, MINW) k_fused_batch_direct(const BatchInst
     const BatchInst& d = inst[it.x];
     const PlaneView in{{d.S[parity]}}, out{{d.S[parity ^ 1]}};
     unsigned st = 0;
-    fused_tile<float, PolPert<float>, TX, TY, NT, SCHEME, true>(L, in, out, d.comp, d.nx, d.ny, (it.y % d.tiles_x) * TX,
-                                                                (it.y / d.tiles_x) * TY, d.pol, d.lam0, d.lam1, st);
+    fused_tile<float, PolPert<float>, TX, TY, NT, SCHEME, true, RW, (RW > 0)>(
+        L, in, out, d.comp, d.nx, d.ny, (it.y % d.tiles_x) * TX, (it.y / d.tiles_x) * TY, d.pol, d.lam0, d.lam1, st);
     if (st) atomicOr(status, st);
 }
 
@@ -90,31 +90,31 @@ __global__ void __launch_bounds__(256) k_batch_copy(const BatchInst* inst, int n
     }
 }
 
-template <int TX, int TY, int NT, int MINW, int SCHEME>
+template <int TX, int TY, int NT, int MINW, int SCHEME, int RW>
 static hipError_t launch_cfg_s(bool direct, const BatchInst* inst, const int2* work, int nwork, int parity,
                                unsigned* status, int grid, hipStream_t s) {
     const size_t lds = sizeof(FusedTile<float, TX, TY>);
     if (direct)
-        hipLaunchKernelGGL((k_fused_batch_direct<TX, TY, NT, MINW, SCHEME>), dim3(nwork), dim3(NT), lds, s, inst, work,
-                           nwork, parity, status);
+        hipLaunchKernelGGL((k_fused_batch_direct<TX, TY, NT, MINW, SCHEME, RW>), dim3(nwork), dim3(NT), lds, s, inst,
+                           work, nwork, parity, status);
     else
         hipLaunchKernelGGL((k_fused_batch<TX, TY, NT, SCHEME>), dim3(grid), dim3(NT), lds, s, inst, work, nwork, parity,
                            status);
     return hipGetLastError();
 }
 
-template <int TX, int TY, int NT, int MINW = 1>
+template <int TX, int TY, int NT, int MINW = 1, int RW = 0>
 static hipError_t launch_cfg(bool direct, int scheme, const BatchInst* inst, const int2* work, int nwork, int parity,
                              unsigned* status, int grid, hipStream_t s) {
-    return scheme ? launch_cfg_s<TX, TY, NT, MINW, 1>(direct, inst, work, nwork, parity, status, grid, s)
-                  : launch_cfg_s<TX, TY, NT, MINW, 0>(direct, inst, work, nwork, parity, status, grid, s);
+    return scheme ? launch_cfg_s<TX, TY, NT, MINW, 1, RW>(direct, inst, work, nwork, parity, status, grid, s)
+                  : launch_cfg_s<TX, TY, NT, MINW, 0, RW>(direct, inst, work, nwork, parity, status, grid, s);
 }
 
-template <int TX, int TY, int NT, int MINW, int SCHEME>
+template <int TX, int TY, int NT, int MINW, int SCHEME, int RW>
 static hipError_t occupancy_cfg_s(bool direct, int* blocks_per_cu) {
     const size_t lds = sizeof(FusedTile<float, TX, TY>);
     if (direct)
-        return hipFuncSetAttribute((const void*)k_fused_batch_direct<TX, TY, NT, MINW, SCHEME>,
+        return hipFuncSetAttribute((const void*)k_fused_batch_direct<TX, TY, NT, MINW, SCHEME, RW>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipError_t e = hipFuncSetAttribute((const void*)k_fused_batch<TX, TY, NT, SCHEME>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -122,26 +122,28 @@ static hipError_t occupancy_cfg_s(bool direct, int* blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused_batch<TX, TY, NT, SCHEME>, NT, lds);
 }
 
-template <int TX, int TY, int NT, int MINW = 1>
+template <int TX, int TY, int NT, int MINW = 1, int RW = 0>
 static hipError_t occupancy_cfg(bool direct, int scheme, int* blocks_per_cu) {
-    return scheme ? occupancy_cfg_s<TX, TY, NT, MINW, 1>(direct, blocks_per_cu)
-                  : occupancy_cfg_s<TX, TY, NT, MINW, 0>(direct, blocks_per_cu);
+    return scheme ? occupancy_cfg_s<TX, TY, NT, MINW, 1, RW>(direct, blocks_per_cu)
+                  : occupancy_cfg_s<TX, TY, NT, MINW, 0, RW>(direct, blocks_per_cu);
 }
 
-// Candidates: six tile shapes in the persistent mode, the same six direct, and 32x8 and
-// 24x13 direct with registers capped for 4 waves per SIMD (two workgroups per CU; 24x13
-// is the single-grid FP32 kernel's shape).
+// Candidates: six tile shapes in the persistent mode, the same six direct, 32x8 and
+// 24x13 direct with registers capped for 4 waves per SIMD (two workgroups per CU), and
+// 31x10 direct, capped, with the targets in rows of 32 lanes and the run-time family
+// (the single-grid FP32 kernel's configuration).
 const BatchTileCfg kBatchCfgs[kNumBatchCfgs] = {
-    {32, 8, 512, false, 1}, {32, 8, 256, false, 1}, {32, 16, 512, false, 1}, {32, 16, 256, false, 1},
-    {64, 8, 512, false, 1}, {16, 16, 256, false, 1}, {32, 8, 512, true, 1},   {32, 8, 256, true, 1},
-    {32, 16, 512, true, 1}, {32, 16, 256, true, 1},  {64, 8, 512, true, 1},   {16, 16, 256, true, 1},
-    {32, 8, 512, true, 4},  {24, 13, 512, true, 4},
+    {32, 8, 512, false, 1, 0}, {32, 8, 256, false, 1, 0}, {32, 16, 512, false, 1, 0}, {32, 16, 256, false, 1, 0},
+    {64, 8, 512, false, 1, 0}, {16, 16, 256, false, 1, 0}, {32, 8, 512, true, 1, 0},   {32, 8, 256, true, 1, 0},
+    {32, 16, 512, true, 1, 0}, {32, 16, 256, true, 1, 0},  {64, 8, 512, true, 1, 0},   {16, 16, 256, true, 1, 0},
+    {32, 8, 512, true, 4, 0},  {24, 13, 512, true, 4, 0},  {31, 10, 512, true, 4, 32},
 };
 
 #define AF_BATCH_SWITCH(F, ...)                                   \
     {                                                             \
         if (cfg == 12) return F<32, 8, 512, 4>(true, __VA_ARGS__); \
         if (cfg == 13) return F<24, 13, 512, 4>(true, __VA_ARGS__); \
+        if (cfg == 14) return F<31, 10, 512, 4, 32>(true, __VA_ARGS__); \
         const bool direct = cfg >= 6;                             \
         switch (cfg % 6) {                                        \
             case 0: return F<32, 8, 512>(direct, __VA_ARGS__);    \

@@ -40,7 +40,7 @@ ROOT = os.path.dirname(HERE)
 
 # Files whose change invalidates a stored counter measurement of a kernel (its
 # sources, and the build script that holds the compiler flags), relative to the package.
-_STEP = ["csrc/af_fused.h", "csrc/af_kernels.h", "csrc/af_device.h", "csrc/af_blocks.h", "csrc/af_internal.h",
+_STEP = ["csrc/af_fused.h", "csrc/af_tile.h", "csrc/af_kernels.h", "csrc/af_device.h", "csrc/af_blocks.h", "csrc/af_internal.h",
          "build.py"]
 _ADJ = ["csrc/af_adjoint.hip", "csrc/af_adjoint.h", "csrc/af_kernels.h", "csrc/af_device.h", "csrc/af_blocks.h",
         "csrc/af_internal.h", "build.py"]
@@ -48,8 +48,8 @@ _ADJ = ["csrc/af_adjoint.hip", "csrc/af_adjoint.h", "csrc/af_kernels.h", "csrc/a
 ADJOINT_KERNELS = ["af::k_adj_fwd", "af::k_adj_points<0, 8, 8, 2>", "af::k_adj_incr"]
 KERNEL_SOURCES = {
     "af::k_fused<double, af::PolAbs<double>, 31, 10, 512, 0, false, 1, 32, true>": ["csrc/af_fused.hip"] + _STEP,
-    "af::k_fused<float, af::PolPert<float>, 24, 13, 512, 0, true, 4, 0, false>": ["csrc/af_fused_f32.hip"] + _STEP,
-    "af::k_fused_batch_direct<24, 13, 512, 4, 0>": ["csrc/af_batch.hip", "csrc/af_batch.h"] + _STEP,
+    "af::k_fused<float, af::PolPert<float>, 31, 10, 512, 0, true, 4, 32, true>": ["csrc/af_fused_f32.hip"] + _STEP,
+    "af::k_fused_batch_direct<31, 10, 512, 4, 0, 32>": ["csrc/af_batch.hip", "csrc/af_batch.h"] + _STEP,
     **{k: _ADJ for k in ADJOINT_KERNELS},
 }
 

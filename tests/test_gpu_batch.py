@@ -57,7 +57,7 @@ def single(torch_dev, P, x, dt, n, scheme="tai"):
     return y
 
 
-@pytest.mark.parametrize("cfg", list(range(14)))
+@pytest.mark.parametrize("cfg", list(range(15)))
 def test_batch_tile_cfg_matches_single_grid(torch_dev, cfg, monkeypatch):
     torch, dev = torch_dev
     from paper_2605_12915_amd.stepper import Batch
@@ -77,7 +77,7 @@ def test_batch_tile_cfg_matches_single_grid(torch_dev, cfg, monkeypatch):
         assert d == 0.0, f"instance {q} ({Ps[q].nx}x{Ps[q].ny}): max diff {d}"
 
 
-@pytest.mark.parametrize("cfg", [0, 13])
+@pytest.mark.parametrize("cfg", [0, 13, 14])
 def test_batch_rb_scheme(torch_dev, orc, cfg, monkeypatch):
     """Additive (RB) point update in both grid modes: bitwise equal to the single-grid
     FP32 RB kernel, and within the FP32 bound of the oracle's RB step."""
