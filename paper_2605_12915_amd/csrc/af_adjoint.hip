@@ -174,6 +174,16 @@ struct IntAcc {
     }
 };
 
+// XCD-aware workgroup numbering (as in the step kernels): workgroup b runs on XCD
+// b mod 8; each XCD takes a contiguous run of the row-major block list, so that the
+// overlapping halos and accumulation windows of neighbouring blocks meet in one L2.
+__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
+    const int xcd = b & 7;
+    int base = 0;
+    for (int x = 0; x < xcd; ++x) base += (ntiles - x + 7) >> 3;
+    return base + (b >> 3);
+}
+
 constexpr int kFBX = 32, kFBY = 8, kFNT = kFBX * kFBY;
 using FwdTile = IntTile<kFBX, kFBY>;
 
@@ -181,10 +191,11 @@ using FwdTile = IntTile<kFBX, kFBY>;
 struct AvgPlanes { const double* src[4]; double* dst[4]; };
 
 __global__ void __launch_bounds__(kFNT, 2) k_adj_fwd(StatePtrs<double> prim, double* C, double* D, PlaneList Z,
-                                                     int nzero, AvgPlanes avg, int nx, int ny, double gamma,
-                                                     double lam0, double lam1, unsigned* status) {
+                                                     int nzero, AvgPlanes avg, int nx, int ny, int tiles_x, int ntiles,
+                                                     double gamma, double lam0, double lam1, unsigned* status) {
     __shared__ FwdTile L;
-    const int i0 = blockIdx.x * kFBX, j0 = blockIdx.y * kFBY, tid = threadIdx.x;
+    const int tile = xcd_tile(blockIdx.x, ntiles), tid = threadIdx.x;
+    const int i0 = (tile % tiles_x) * kFBX, j0 = (tile / tiles_x) * kFBY;
     const size_t N = (size_t)nx * ny;
     const int ox = tid % kFBX, oy = tid / kFBX;
     const bool own = i0 + ox < nx && j0 + oy < ny;
@@ -297,11 +308,12 @@ struct PointBlock {
 template <int SCHEME, int BX, int BY, int MINB>
 __global__ void __launch_bounds__(3 * BX * BY, MINB)
     k_adj_points(StatePtrs<double> prim, const double* C, const double* Dfwd, StatePtrs<double> cot1, PlaneList G,
-                 int nx, int ny, double gamma, double lam0, double lam1) {
+                 int nx, int ny, int tiles_x, int ntiles, double gamma, double lam0, double lam1) {
     using B = PointBlock<BX, BY>;
     extern __shared__ __align__(16) unsigned char smem[];
     double* stage = reinterpret_cast<double*>(smem);   // [40][RY][RX]
-    const int i0 = blockIdx.x * BX, j0 = blockIdx.y * BY;
+    const int tile = xcd_tile(blockIdx.x, ntiles);
+    const int i0 = (tile % tiles_x) * BX, j0 = (tile / tiles_x) * BY;
     const LdsWin<40, B::RX, B::RY> O{stage + 40 * B::WIN, i0 - 1, j0 - 1};
     O.zero();
     if (threadIdx.x < B::WIN) {
@@ -343,9 +355,9 @@ template <int SCHEME, int BX, int BY, int MINB>
 void launch_points(const StepArgs& a, StatePtrs<double> prim, const double* C, const double* Dfwd,
                    StatePtrs<double> cot1, const PlaneList& L, double lam0, double lam1) {
     using B = PointBlock<BX, BY>;
-    dim3 grd((a.nx + BX - 1) / BX, (a.ny + BY - 1) / BY);
-    hipLaunchKernelGGL((k_adj_points<SCHEME, BX, BY, MINB>), grd, dim3(B::NT), B::LDS, a.stream, prim, C, Dfwd, cot1,
-                       L, a.nx, a.ny, a.gamma, lam0, lam1);
+    const int tx = (a.nx + BX - 1) / BX, nt = tx * ((a.ny + BY - 1) / BY);
+    hipLaunchKernelGGL((k_adj_points<SCHEME, BX, BY, MINB>), dim3(nt), dim3(B::NT), B::LDS, a.stream, prim, C, Dfwd,
+                       cot1, L, a.nx, a.ny, tx, nt, a.gamma, lam0, lam1);
 }
 
 template <int BX, int BY, int MINB>
@@ -372,9 +384,11 @@ using IncrWin = LdsWin<20, kIBX + 2, kIBY + 2>;   // planes 0..15 as the point w
 
 __global__ void __launch_bounds__(kIBX * kIBY, 2) k_adj_incr(StatePtrs<double> prim, const double* C, const double* lD,
                                                           const double* lC, PlaneList G, int nx, int ny,
-                                                          double gamma, double lam0, double lam1) {
+                                                          int tiles_x, int ntiles, double gamma, double lam0,
+                                                          double lam1) {
     __shared__ double win[20 * (kIBX + 2) * (kIBY + 2)];
-    const int i0 = blockIdx.x * kIBX, j0 = blockIdx.y * kIBY;
+    const int tile = xcd_tile(blockIdx.x, ntiles);
+    const int i0 = (tile % tiles_x) * kIBX, j0 = (tile / tiles_x) * kIBY;
     const IncrWin O{win, i0 - 1, j0 - 1};
     O.zero();
     __syncthreads();
@@ -441,9 +455,9 @@ hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1_[16], vo
     for (int k = 0; k < 4; ++k) { avg.src[k] = cot1.p[k]; avg.dst[k] = cot0.p[k]; }
     const double lam1 = a.dt / a.h, lam0 = 0.5 * lam1;
     {
-        dim3 grd((a.nx + kFBX - 1) / kFBX, (a.ny + kFBY - 1) / kFBY);
-        hipLaunchKernelGGL(k_adj_fwd, grd, dim3(kFNT), 0, a.stream, prim, C, Dfwd, L, np, avg, a.nx, a.ny, a.gamma,
-                           lam0, lam1, a.status);
+        const int tx = (a.nx + kFBX - 1) / kFBX, nt = tx * ((a.ny + kFBY - 1) / kFBY);
+        hipLaunchKernelGGL(k_adj_fwd, dim3(nt), dim3(kFNT), 0, a.stream, prim, C, Dfwd, L, np, avg, a.nx, a.ny, tx, nt,
+                           a.gamma, lam0, lam1, a.status);
     }
     if (a.ev_begin) (void)hipEventRecord(a.ev_begin, a.stream);
     // point kernel: 8x8-cell blocks, two per CU (16x8 blocks at one per CU, whose
@@ -451,9 +465,9 @@ hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1_[16], vo
     if (a.scheme == 0) launch_points<0, 8, 8, 2>(a, prim, C, Dfwd, cot1, L, lam0, lam1);
     else launch_points<1, 8, 8, 2>(a, prim, C, Dfwd, cot1, L, lam0, lam1);
     {
-        dim3 grd((a.nx + kIBX - 1) / kIBX, (a.ny + kIBY - 1) / kIBY);
-        hipLaunchKernelGGL(k_adj_incr, grd, dim3(kIBX * kIBY), 0, a.stream, prim, C, lD, lC, Li, a.nx, a.ny, a.gamma,
-                           lam0, lam1);
+        const int tx = (a.nx + kIBX - 1) / kIBX, nt = tx * ((a.ny + kIBY - 1) / kIBY);
+        hipLaunchKernelGGL(k_adj_incr, dim3(nt), dim3(kIBX * kIBY), 0, a.stream, prim, C, lD, lC, Li, a.nx, a.ny, tx, nt,
+                           a.gamma, lam0, lam1);
     }
     if (a.ev_end) (void)hipEventRecord(a.ev_end, a.stream);
     return hipGetLastError();

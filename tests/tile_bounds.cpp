@@ -8,7 +8,7 @@
 // velocities up to 1.5 cells per step, so that feet leave the window's reach and the
 // foot guard must clamp them.
 //
-// Build (host only): see tests/test_host_bounds.py.
+// Build (host only, under the sanitizers): tests/test_sanitize.py.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -158,8 +158,10 @@ int main() {
     for (const auto& gr : grids)
         for (double vmax : {0.4, 0.95, 1.5})
             for (int scheme = 0; scheme < 2; ++scheme) {
-                // the FP64 tile (31 x 10, target rows of 32 lanes) and the FP32 one (24 x 13, tight rows)
+                // the single-grid tiles (31 x 10, target rows of 32 lanes) in both precisions, and a
+                // tight-row tile
                 walk_grid<double, 31, 10, 32, 512>(gr[0], gr[1], vmax, seed++, scheme);
+                walk_grid<float, 31, 10, 32, 512>(gr[0], gr[1], vmax, seed++, scheme);
                 walk_grid<float, 24, 13, 0, 512>(gr[0], gr[1], vmax, seed++, scheme);
                 // the batched kernel's candidate shapes at the extremes of their aspect ratio
                 walk_grid<float, 64, 8, 0, 512>(gr[0], gr[1], vmax, seed++, scheme);
