@@ -126,6 +126,54 @@ def test_f32_rollback_keeps_compensation(torch_dev):
     assert torch.equal(x, y)
 
 
+def test_f32_trajectory_compensation(torch_dev):
+    """The Kahan compensation continues only along a trajectory: a call whose input is
+    the previous call's output continues it (the result equals one call of several
+    steps), any other input restarts it at zero (stepping out of one state twice gives
+    the same result both times), af_reset_trajectory restarts it, and af_time_steps
+    leaves it alone."""
+    torch, dev = torch_dev
+    from paper_2605_12915_amd import _lib
+    from paper_2605_12915_amd.stepper import Stepper, to_perturbation
+    P = I.random_smooth(40, 32, seed=5, amp=0.1, vel=(0.3, 0.2))
+    s0 = to_perturbation(P.state(), P.bg, P.gamma)
+    dt = P.dt_for_cfl(0.4)
+
+    def fresh():
+        return Stepper(P.nx, P.ny, P.h, P.gamma, precision="f32", bg=P.bg, device=dev)
+
+    x0 = torch.from_numpy(s0).to(dev)
+    ref = fresh()
+    r2 = ref.step(x0.clone(), dt, 2)
+    # out-of-place ping-pong continues the trajectory
+    a = fresh()
+    y1 = a.step_out(x0, dt)
+    y2 = a.step_out(y1, dt)
+    assert torch.equal(y2, r2)
+    # the same one-step state stepped by a fresh context (zero compensation) differs:
+    # the compensation is observable at this size
+    z2 = fresh().step_out(y1, dt)
+    assert not torch.equal(z2, r2)
+    # stepping out of one state twice restarts the compensation each time
+    b = fresh()
+    u1 = b.step_out(x0, dt)
+    u1b = b.step_out(x0, dt)
+    assert torch.equal(u1, u1b) and torch.equal(u1, y1)
+    # af_reset_trajectory: the next in-place step starts from zero compensation
+    c = fresh()
+    w = c.step(x0.clone(), dt, 1)
+    w_copy = w.clone()
+    _lib.check(_lib.lib().af_reset_trajectory(c._ctx), "af_reset_trajectory")
+    c.step(w, dt, 1)
+    assert torch.equal(w, fresh().step(w_copy, dt, 1))
+    # af_time_steps runs on copies with compensation of its own
+    d = fresh()
+    v = d.step(x0.clone(), dt, 1)
+    d.time_steps(v, dt, 3)
+    d.step(v, dt, 1)
+    assert torch.equal(v, r2)
+
+
 def test_f32_conservation(torch_dev):
     P = I.random_smooth(48, 40, seed=2, amp=0.2)
     s0 = P.state()
