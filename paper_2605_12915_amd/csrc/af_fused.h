@@ -4,8 +4,6 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-
 #include "af_internal.h"
 #include "af_kernels.h"
 #include "af_tile.h"
@@ -25,13 +23,11 @@ __device__ __forceinline__ void store_prim(const SP& o, size_t g, const Prim<T>&
 // tiles of many grids per workgroup).  The arithmetic of every node does not depend
 // on the tile shape or on which kernel calls it; compiled with -ffp-contract=on in
 // both, the FP32 kernels therefore agree bit for bit.
-// kFamilyFence: phase 2 computes the four families' increments one after the other
-// with a scheduling fence between them.  Interleaving them (the compiler's choice
-// without it) needs more registers than a wave holds at these occupancies and spills:
-// in FP64 beyond 256, in the FP32 single-grid kernel (128 at two workgroups per CU)
-// 14 registers, whose scratch traffic reached HBM (1.9x the algorithmic bytes written).
-// The fence leaves 2 there and is 3.5% faster.  The batched FP32 kernels, whose plane
-// pointers come from a descriptor in global memory, are 1% faster without it.
+// Phase 2 computes the four families' increments one after the other with a
+// scheduling fence between them.  Interleaving them (the compiler's choice without it)
+// needs more registers than a wave holds at these occupancies and spills: in FP64
+// beyond 256, in the FP32 kernels (128 at two workgroups per CU) 14 registers, whose
+// scratch traffic reached HBM (1.9x the algorithmic bytes written).
 //
 // SP: any type with a member p such that p[k] is plane k's pointer (StatePtrs, or a
 // view of a descriptor in global memory whose pointers are loaded where used).
@@ -110,7 +106,6 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
     __syncthreads();
 
     // ---- phase 2: increments at node-cells [-1, T+2)^2, both durations ---------------
-    constexpr bool kFamilyFence = sizeof(T) == 8 || std::is_same<SP, StatePtrs<T>>::value;
     {
         LdsAcc<T, TX, TY> A{&L};
         for (int e = tid; e < Tile::SD * Tile::DY; e += NT) {
@@ -122,19 +117,19 @@ __device__ __forceinline__ void fused_tile(FusedTile<T, TX, TY>& L, const SP& in
             for (int t = 0; t < 2; ++t)
 #pragma unroll
                 for (int v = 0; v < 3; ++v) L.D[t][0 * 3 + v][y + 1][x + 1] = d[t][v];
-            if constexpr (kFamilyFence) __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_sched_barrier(0);   // one family at a time
             node_increments<F_EV>(A, x, y, pol, lam0, lam1, d, st);
 #pragma unroll
             for (int t = 0; t < 2; ++t)
 #pragma unroll
                 for (int v = 0; v < 3; ++v) L.D[t][1 * 3 + v][y + 1][x + 1] = d[t][v];
-            if constexpr (kFamilyFence) __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_sched_barrier(0);   // one family at a time
             node_increments<F_EH>(A, x, y, pol, lam0, lam1, d, st);
 #pragma unroll
             for (int t = 0; t < 2; ++t)
 #pragma unroll
                 for (int v = 0; v < 3; ++v) L.D[t][2 * 3 + v][y + 1][x + 1] = d[t][v];
-            if constexpr (kFamilyFence) __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_sched_barrier(0);   // one family at a time
             node_increments<F_C>(A, x, y, pol, lam0, lam1, d, st);
 #pragma unroll
             for (int t = 0; t < 2; ++t)

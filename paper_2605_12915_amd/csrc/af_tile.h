@@ -8,20 +8,18 @@
 
 namespace af {
 
-// FP64: P, C and D share one row stride (PX), and phases 1 and 2 walk their items in
-// rows of that stride (the items past a region's width idle), so the lanes of a wave
-// read consecutive LDS words of every plane instead of colliding on banks where the
-// rows of the item grid and of the array wrap at different widths (2% faster).  The
-// FP32 instantiation keeps tight rows: its 128-register budget spills with the
-// strided loops.
+// P, C and D share one row stride (PX), and phases 1 and 2 walk their items in rows of
+// that stride (the items past a region's width idle), so the lanes of a wave read
+// consecutive LDS words of every plane instead of colliding on banks where the rows of
+// the item grid and of the array wrap at different widths (FP64 2% faster; FP32 4.6%,
+// its bank-conflict cycles had outnumbered its active LDS cycles).
 template <class T, int TX, int TY>
 struct FusedTile {
     static constexpr int PX = TX + 5, PY = TY + 5;   // primitives: cells [-2, T+3)
     static constexpr int CX = TX + 4, CY = TY + 4;   // centres:    cells [-2, T+2)
     static constexpr int DX = TX + 3, DY = TY + 3;   // increments: node-cells [-1, T+2)
     static constexpr int VX = TX + 1, VY = TY + 1;   // flux nodes: node-cells [0, T]
-    static constexpr bool kCommon = sizeof(T) == 8;
-    static constexpr int SC = kCommon ? PX : CX, SD = kCommon ? PX : DX;   // row strides of C, D
+    static constexpr int SC = PX, SD = PX;           // row strides of C, D
     T P[12][PY][PX];
     T C[4][CY][SC];
     union {
