@@ -31,7 +31,10 @@ data's cells share, and each crossing line adds the chord term
     (1 / (2 pi r)) int_0^pi [g](point of the chord at angle phi) dphi   (normal n).
 The paper evaluates these integrals in closed form from full-disk, single-cap and
 double-cap moments (eq. fc-moment-families, eq. fc-cap-moments, eq. fc-role-rows).
-Here they are integrated numerically, split exactly along the grid lines that cut
+Here they are integrated numerically.  The history term is first rewritten exactly as
+one integral over the disk of radius R (see exact_acoustic), which needs neither the
+radius integral nor the chord terms; history_by_radius keeps the form above as a
+cross-check.  The disk integrals are split exactly along the grid lines that cut
 the disk: in polar coordinates about F with rho = sin(psi) (which absorbs the
 weight), the angle split where a grid line becomes tangent to the circle or passes
 through a corner, the radius split where each ray crosses a line, and the radius
@@ -246,14 +249,38 @@ def chord_nodes(F, r):
 
 def exact_acoustic(F, R, fpi, fu, fv):
     """(pi, u, v) at F after the frozen acoustic evolution over the radius R (cell
-    units) from continuous piecewise-Q2 data pi_0 = fpi, u_0 = fu, v_0 = fv."""
+    units) from continuous piecewise-Q2 data pi_0 = fpi, u_0 = fu, v_0 = fv.
+
+    The history term int_0^R r M_r[grad g] dr is taken as one disk integral:
+    exchanging the order of integration turns it into (1 / 2 pi) int_{|y| < R}
+    grad g(F + y) arccosh(R / |y|) dy, and integrating by parts piece by piece (the
+    weight vanishes on the circle; the jump terms of the distributional gradient
+    cancel the pieces' boundary terms along the grid lines) into
+    (R / 2 pi) int_0^{2 pi} e_theta int_0^{pi/2} g(F + R sin(psi) e_theta) dpsi dtheta,
+    i.e. R sum w g z / |z|^2 over the same nodes as M_R.  history_by_radius evaluates
+    the original form (radius integral of spherical means plus chord terms) for the
+    pins."""
     Fx, Fy = F
     X, Y, zx, zy, w = disk_nodes(F, R)
     pi0 = fpi.eval(X, Y)
     px, py = fpi.eval(X, Y, (1, 0)), fpi.eval(X, Y, (0, 1))
     g = fu.eval(X, Y, (1, 0)) + fv.eval(X, Y, (0, 1))
     pi = np.sum(w * pi0) + R * np.sum(w * (zx * px + zy * py)) - R * np.sum(w * g)
+    z2 = zx * zx + zy * zy
+    hist = np.array([R * np.sum(w * g * zx / z2), R * np.sum(w * g * zy / z2)])
+    u = float(fu.eval(np.array(Fx), np.array(Fy))) - R * np.sum(w * px) + hist[0]
+    v = float(fv.eval(np.array(Fx), np.array(Fy))) - R * np.sum(w * py) + hist[1]
+    return np.array([float(pi), u, v])
 
+
+def history_by_radius(F, R, fu, fv):
+    """int_0^R r M_r[grad g] dr, g = div u_0, as written in App. C: spherical means of
+    the regular part of grad g at Gauss radii (split at every radius where a line or a
+    corner enters the disk) plus, for each grid line crossing the disk of radius r, the
+    chord integral of the jump of g (the singular part of the distributional gradient).
+    Converges more slowly than the form exact_acoustic uses where lines pass close to
+    F (raise NQ_THETA, NQ_RHO, NQ_R)."""
+    Fx, Fy = F
     def g_at(XX, YY, ci, cj):
         return fu.eval(XX, YY, (1, 0), ci, cj) + fv.eval(XX, YY, (0, 1), ci, cj)
 
@@ -301,9 +328,7 @@ def exact_acoustic(F, R, fpi, fu, fv):
     hist = np.zeros(2)
     for q, r in enumerate(radii):
         hist += rw[q] * r * (np.array([gx[q], gy[q]]) + line[q])
-    u = float(fu.eval(np.array(Fx), np.array(Fy))) - R * np.sum(w * px) + hist[0]
-    v = float(fv.eval(np.array(Fx), np.array(Fy))) - R * np.sum(w * py) + hist[1]
-    return np.array([float(pi), u, v])
+    return hist
 
 
 # ---------------------------------------------------------------------------------

@@ -11,9 +11,11 @@ other means:
     caps; data varying in x plus data varying in y (both lines and the double cap);
   * a disk centred on a node: the Poisson-formula helper tests/q2field.poisson_node
     and the node-centred operator of the C++ oracle (App. D blocks).
-The step built on it is pinned by free-stream preservation, discrete conservation,
-and the fluid at rest, where the foot is the node and the update must equal the
-transported (node-centred) update of the C++ oracle.
+The history term of the velocity is pinned against the form App. C writes (radius
+integral of spherical means plus chord terms for the jumps of div u).  The step built
+on it is pinned by free-stream preservation, discrete conservation, and the fluid at
+rest, where the foot is the node and the update must equal the transported
+(node-centred) update of the C++ oracle.
 """
 import math
 
@@ -125,6 +127,37 @@ def test_node_centred_disk_equals_poisson_helper():
             want = q.poisson_node(fq[0], fq[1], fq[2], K, lines, 1.0, R)
             got = fc.exact_acoustic(K, R, fl[0], fl[1], fl[2])
             assert np.abs(got - want).max() <= 1e-11 * max(1.0, np.abs(want).max()), (K, R, got, want)
+
+
+def _history_parts(F, R, fu, fv):
+    X, Y, zx, zy, w = fc.disk_nodes(F, R)
+    g = fu.eval(X, Y, (1, 0)) + fv.eval(X, Y, (0, 1))
+    z2 = zx * zx + zy * zy
+    return np.array([R * np.sum(w * g * zx / z2), R * np.sum(w * g * zy / z2)])
+
+
+def test_history_forms_agree(monkeypatch):
+    """The history term of the velocity, int_0^R r M_r[grad g] dr: the disk form that
+    exact_acoustic uses (exchange of the integration order, then integration by parts)
+    equals the form written in App. C (spherical means of grad g at Gauss radii plus
+    the chord integrals of the jumps of g = div u_0 across grid lines), here at raised
+    quadrature orders, for general continuous piecewise-Q2 data (random nodal values)
+    with grid lines and a corner close to the foot.  The disk form is converged at the
+    default orders (unchanged to 1e-15 when they are raised)."""
+    rng = np.random.default_rng(12)
+    fu, fv = (fc.Q2Lattice(rng.normal(size=(16, 16))) for _ in range(2))
+    cases = [((3.02, 3.97), 0.45), ((3.9, 4.05), 0.45), ((3.1, 3.05), 0.3), ((3.3, 4.2), 0.45)]
+    default = [_history_parts(F, R, fu, fv) for F, R in cases]
+    monkeypatch.setattr(fc, "NQ_THETA", 64)
+    monkeypatch.setattr(fc, "NQ_RHO", 20)
+    monkeypatch.setattr(fc, "NQ_R", 24)
+    monkeypatch.setattr(fc, "_GL", {})
+    for (F, R), d in zip(cases, default):
+        parts = _history_parts(F, R, fu, fv)
+        radius = fc.history_by_radius(F, R, fu, fv)
+        scale = max(1.0, np.abs(parts).max())
+        assert np.abs(parts - d).max() <= 1e-14 * scale, (F, R, parts, d)
+        assert np.abs(parts - radius).max() <= 1e-10 * scale, (F, R, parts, radius)
 
 
 def test_fluid_at_rest_equals_transported_update(orc):
