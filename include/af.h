@@ -43,7 +43,9 @@ enum {
     AF_ERR_FOOT = 4,         /* some convective foot moved one cell or more */
     AF_ERR_NONPHYSICAL = 5,  /* rho <= 0 or p <= 0 at a node or recovered centre, or NaN */
     AF_ERR_UNSUPPORTED = 6,  /* operation not available for this context's precision */
-    AF_ERR_SCRATCH = 7       /* grid larger than the fixed scratch of af_step_adjoint_noalloc */
+    AF_ERR_SCRATCH = 7,      /* grid larger than the fixed scratch of af_step_adjoint_noalloc */
+    AF_ERR_FOOTPRINT = 8     /* AF_SCHEME_FC: a disk of radius c* tau / h about a foot leaves the
+                                half-cell footprint |F - P| + R < h/2 (App. C, eq. fc-half-footprint) */
 };
 
 enum { AF_F64 = 0, AF_F32 = 1 };
@@ -51,8 +53,16 @@ enum { AF_F64 = 0, AF_F32 = 1 };
 enum {
     AF_CHECK = 1,       /* af_step reads back the device status flag after each call
                            (one host synchronisation per call) and returns the error */
-    AF_SCHEME_RB = 2    /* additive RB point update (eq. barsukow-additive) instead of
+    AF_SCHEME_RB = 2,   /* additive RB point update (eq. barsukow-additive) instead of
                            the transported-increment update (eq. transported-update) */
+    AF_SCHEME_FC = 4    /* foot-centred exact frozen-acoustic point update (App. C; Sec. 4,
+                           the paragraph on an exact frozen acoustic update): the frozen
+                           state taken at the convective foot and the exact solution of the
+                           frozen acoustic system evaluated there by quadrature of spherical
+                           means; density from the linear closure.  An analytical reference
+                           several hundred times the transported update's cost.  AF_F64
+                           single-grid contexts only, not with AF_SCHEME_RB; no adjoint.
+                           Fails with AF_ERR_FOOTPRINT when |F - P| + c* tau / h >= 1/2 */
 };
 
 typedef struct af_config {
@@ -63,7 +73,7 @@ typedef struct af_config {
     int32_t precision;   /* AF_F64 or AF_F32 */
     double bg[4];        /* AF_F32: background primitive state (rho, u, v, p) about which
                             the float planes hold perturbations; ignored for AF_F64 */
-    int32_t flags;       /* AF_CHECK | AF_SCHEME_RB */
+    int32_t flags;       /* AF_CHECK | AF_SCHEME_RB or AF_SCHEME_FC */
 } af_config;
 
 typedef struct af_state {

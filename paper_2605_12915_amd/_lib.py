@@ -9,9 +9,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaf.so")
 
 (AF_OK, AF_ERR_ARG, AF_ERR_HIP, AF_ERR_ACOUSTIC_CFL, AF_ERR_FOOT, AF_ERR_NONPHYSICAL, AF_ERR_UNSUPPORTED,
- AF_ERR_SCRATCH) = range(8)
+ AF_ERR_SCRATCH, AF_ERR_FOOTPRINT) = range(9)
 AF_F64, AF_F32 = 0, 1
-AF_CHECK, AF_SCHEME_RB = 1, 2
+AF_CHECK, AF_SCHEME_RB, AF_SCHEME_FC = 1, 2, 4
+SCHEME_FLAGS = {"tai": 0, "rb": AF_SCHEME_RB, "fc": AF_SCHEME_FC}
 
 EXPORTED = [
     "af_init", "af_step", "af_step_out", "af_read_status", "af_step_adjoint", "af_diagnostics",

@@ -51,6 +51,7 @@ def _compile(src: str, verbose: bool) -> str:
 
 def build(verbose: bool = False) -> str:
     subprocess.run([sys.executable, os.path.join(CSRC, "gen_blocks.py")], check=True)
+    subprocess.run([sys.executable, os.path.join(CSRC, "gen_gauss.py")], check=True)
     os.makedirs(OBJ, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:

@@ -132,6 +132,7 @@ af_status status_from_bits(unsigned b) {
     if (b & af::SB_NONPHYS) return AF_ERR_NONPHYSICAL;
     if (b & af::SB_CFL) return AF_ERR_ACOUSTIC_CFL;
     if (b & af::SB_FOOT) return AF_ERR_FOOT;
+    if (b & af::SB_FOOTPRINT) return AF_ERR_FOOTPRINT;
     return AF_OK;
 }
 
@@ -153,6 +154,7 @@ hipError_t launch_step(af_ctx* c, void* const in[16], void* const out[16], doubl
     for (int k = 0; k < 4; ++k) a.bg[k] = c->cfg.bg[k];
     a.comp = c->comp;
     if (c->f32) return af::launch_step_fused_f32(a);
+    if (c->variant == 3) return af::launch_step_fc_f64(a);
     if (c->variant == 1) return af::launch_step_multi_f64(a);
     if (c->variant == 2) return af::launch_step_split_f64(a);
     return af::launch_step_fused_f64(a);
@@ -409,6 +411,7 @@ const char* af_status_string(af_status s) {
         case AF_ERR_NONPHYSICAL: return "non-physical state (rho <= 0, p <= 0 or NaN)";
         case AF_ERR_UNSUPPORTED: return "operation not supported for this precision";
         case AF_ERR_SCRATCH: return "grid larger than the static scratch of the allocation-free entry point";
+        case AF_ERR_FOOTPRINT: return "foot-centred update: disk about a foot leaves the half-cell footprint";
         default: return "unknown status";
     }
 }
@@ -429,6 +432,8 @@ af_status af_init(const af_config* cfg, void* hip_stream, af_ctx** out) {
     if ((uint64_t)cfg->nx * (uint64_t)cfg->ny > kMaxCells) return AF_ERR_ARG;
     if (cfg->precision != AF_F64 && cfg->precision != AF_F32) return AF_ERR_ARG;
     if (cfg->precision == AF_F32 && (!(cfg->bg[0] > 0.0) || !(cfg->bg[3] > 0.0))) return AF_ERR_ARG;
+    if ((cfg->flags & AF_SCHEME_FC) && (cfg->flags & AF_SCHEME_RB)) return AF_ERR_ARG;
+    if ((cfg->flags & AF_SCHEME_FC) && cfg->precision != AF_F64) return AF_ERR_UNSUPPORTED;
     af_ctx* c = new (std::nothrow) af_ctx();
     if (!c) return AF_ERR_ARG;
     c->cfg = *cfg;
@@ -442,8 +447,10 @@ af_status af_init(const af_config* cfg, void* hip_stream, af_ctx** out) {
     if (v && std::strcmp(v, "multi") == 0) c->variant = 1;
     if (v && std::strcmp(v, "split") == 0) c->variant = 2;
     if (c->f32) c->variant = 0;   // the FP32 form has the fused kernel only
+    if (cfg->flags & AF_SCHEME_FC) c->variant = 3;   // the foot-centred update: multi-kernel path
     size_t sbytes = 16;
     if (c->variant == 1) sbytes = af::scratch_bytes_multi_f64(cfg->nx, cfg->ny);
+    if (c->variant == 3) sbytes = af::scratch_bytes_fc_f64(cfg->nx, cfg->ny);
     if (c->variant == 2) sbytes = af::scratch_bytes_split_f64(cfg->nx, cfg->ny);
     if (e == hipSuccess && c->f32) e = af::prepare_fused_f32();
     if (e == hipSuccess && c->f32) e = hipMalloc(&c->comp, 4 * c->N * sizeof(float));
@@ -590,7 +597,7 @@ af_status af_step_adjoint(af_ctx* c, const af_state* primal_n, const af_state* c
     if (!c || !state_ok(primal_n) || !state_ok(cot_np1) || !state_ok(cot_n) || !(dt > 0.0) || !std::isfinite(dt))
         return AF_ERR_ARG;
     if (share_plane(cot_n, cot_np1) || share_plane(cot_n, primal_n)) return AF_ERR_ARG;
-    if (c->f32 || c->nbatch) return AF_ERR_UNSUPPORTED;
+    if (c->f32 || c->nbatch || c->variant == 3) return AF_ERR_UNSUPPORTED;
     if (!c->adj_scratch) AF_HIP(hipMalloc(&c->adj_scratch, af::scratch_bytes_adjoint_f64(c->cfg.nx, c->cfg.ny)));
     af::StepArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -619,7 +626,7 @@ af_status af_step_adjoint_noalloc(const af_config* cfg, void* hip_stream, const 
         !std::isfinite(cfg->gamma))
         return AF_ERR_ARG;
     if (share_plane(cot_n, cot_np1) || share_plane(cot_n, primal_n)) return AF_ERR_ARG;
-    if (cfg->precision != AF_F64) return AF_ERR_UNSUPPORTED;
+    if (cfg->precision != AF_F64 || (cfg->flags & AF_SCHEME_FC)) return AF_ERR_UNSUPPORTED;
     if ((uint64_t)cfg->nx * (uint64_t)cfg->ny > af::kNoallocMaxCells) return AF_ERR_SCRATCH;
     af::StepArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -738,7 +745,7 @@ af_status af_init_batch(const af_config* cfgs, int32_t n, void* hip_stream, af_c
             return AF_ERR_ARG;
         total += (uint64_t)cf.nx * (uint64_t)cf.ny;
         if (total > kMaxCells) return AF_ERR_ARG;
-        if (cf.precision != AF_F32) return AF_ERR_UNSUPPORTED;
+        if (cf.precision != AF_F32 || (cf.flags & AF_SCHEME_FC)) return AF_ERR_UNSUPPORTED;
         if (!(cf.bg[0] > 0.0) || !(cf.bg[3] > 0.0)) return AF_ERR_ARG;
         if ((cf.flags & AF_SCHEME_RB) != (cfgs[0].flags & AF_SCHEME_RB)) return AF_ERR_UNSUPPORTED;   // one scheme per batch
     }
@@ -931,6 +938,7 @@ const char* af_dominant_kernel(af_ctx* c) {
     if (c && c->f32)
         return rb ? "af::k_fused<float, af::PolPert<float>, 31, 10, 512, 1, true, 4, 32, true>"
                   : "af::k_fused<float, af::PolPert<float>, 31, 10, 512, 0, true, 4, 32, true>";
+    if (c && c->variant == 3) return "af::k_fc_points";
     if (c && c->variant == 1) return "af_step multi-kernel sequence";
     if (c && c->variant == 2) return rb ? "af::k_points_update<32, 8, 512, 1>" : "af::k_points_update<32, 8, 512, 0>";
     return rb ? "af::k_fused<double, af::PolAbs<double>, 31, 10, 512, 1, false, 1, 32, true>"

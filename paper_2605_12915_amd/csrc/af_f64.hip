@@ -9,8 +9,11 @@
 // This path stores the intermediates (W^C, 24 increment planes, 12 half-time
 // planes) in the context's scratch; the fused kernel in af_fused.hip keeps them
 // on chip.
+// The foot-centred exact update (AF_SCHEME_FC) runs here too: k_centre, then
+// k_fc_points in place of k_incr and k_points, then k_update.
 #include <hip/hip_runtime.h>
 
+#include "af_footcentred.h"
 #include "af_internal.h"
 #include "af_kernels.h"
 
@@ -179,6 +182,36 @@ __global__ void __launch_bounds__(256) k_update(StatePtrs<double> in, const doub
     }
 }
 
+// Foot-centred exact point update (af_footcentred.h) of every target for both
+// durations: item e is duration e / 3N, family (e / N) mod 3, cell e mod N, so that
+// consecutive lanes take consecutive cells of one family and duration.
+__global__ void __launch_bounds__(256) k_fc_points(StatePtrs<double> in, const double* C, double* half,
+                                                   StatePtrs<double> out, int nx, int ny, double gamma, double lam0,
+                                                   double lam1, unsigned* status) {
+    const size_t N = (size_t)nx * ny, total = 6 * N;
+    GAcc64 A{{}, C, nx, ny};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) A.s[k] = in.p[k];
+    unsigned st = 0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int tau = e >= 3 * N ? 1 : 0;
+        const size_t r = e - (size_t)tau * 3 * N;
+        const int fam = (int)(r / N);
+        const size_t c = r - (size_t)fam * N;
+        const int i = (int)(c % nx), j = (int)(c / nx);
+        const Prim<double> w = fc_point_update(A, fam, i, j, gamma, tau ? lam1 : lam0, st);
+        double* const q[4] = {tau ? out.p[4 + 4 * fam] : half + (size_t)(4 * fam) * N,
+                              tau ? out.p[5 + 4 * fam] : half + (size_t)(4 * fam + 1) * N,
+                              tau ? out.p[6 + 4 * fam] : half + (size_t)(4 * fam + 2) * N,
+                              tau ? out.p[7 + 4 * fam] : half + (size_t)(4 * fam + 3) * N};
+        q[0][c] = w.r;
+        q[1][c] = w.u;
+        q[2][c] = w.v;
+        q[3][c] = w.p;
+    }
+    if (st) atomicOr(status, st);
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
@@ -206,5 +239,25 @@ hipError_t launch_step_multi_f64(const StepArgs& a) {
 }
 
 size_t scratch_bytes_multi_f64(int nx, int ny) { return (size_t)nx * ny * (4 + 24 + 12) * sizeof(double); }
+
+hipError_t launch_step_fc_f64(const StepArgs& a) {
+    dim3 blk(64, 4), grd((a.nx + 63) / 64, (a.ny + 3) / 4);
+    StatePtrs<double> in, out;
+    for (int k = 0; k < 16; ++k) { in.p[k] = (double*)a.in[k]; out.p[k] = (double*)a.out[k]; }
+    double* C = (double*)a.scratch;
+    const size_t N = (size_t)a.nx * a.ny;
+    double* half = C + 4 * N;
+    const double lam1 = a.dt / a.h, lam0 = 0.5 * lam1;
+    hipLaunchKernelGGL(k_centre, grd, blk, 0, a.stream, in, C, a.nx, a.ny, a.gamma, a.status);
+    const size_t items = 6 * N, blocks = (items + 255) / 256;
+    if (a.ev_begin) (void)hipEventRecord(a.ev_begin, a.stream);
+    hipLaunchKernelGGL(k_fc_points, dim3((unsigned)(blocks < (1u << 20) ? blocks : (1u << 20))), dim3(256), 0,
+                       a.stream, in, C, half, out, a.nx, a.ny, a.gamma, lam0, lam1, a.status);
+    if (a.ev_end) (void)hipEventRecord(a.ev_end, a.stream);
+    hipLaunchKernelGGL(k_update, grd, blk, 0, a.stream, in, half, out, a.nx, a.ny, a.gamma, lam1);
+    return hipGetLastError();
+}
+
+size_t scratch_bytes_fc_f64(int nx, int ny) { return (size_t)nx * ny * (4 + 12) * sizeof(double); }
 
 }  // namespace af

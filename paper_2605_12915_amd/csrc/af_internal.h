@@ -6,7 +6,8 @@
 
 namespace af {
 
-enum StatusBits { SB_CFL = 1, SB_FOOT = 2, SB_NONPHYS = 4 };
+// SB_FOOTPRINT: the foot-centred update's disk leaves the half-cell footprint.
+enum StatusBits { SB_CFL = 1, SB_FOOT = 2, SB_NONPHYS = 4, SB_FOOTPRINT = 8 };
 
 template <class T>
 struct StatePtrs { T* p[16]; };
@@ -37,6 +38,10 @@ DiagBg diag_bg(bool f32, const double bg[4], double gamma);
 hipError_t launch_diag_final(const double* partials, int n, double* out9, hipStream_t stream);
 
 hipError_t launch_step_multi_f64(const StepArgs& a);
+// Foot-centred exact point update (App. C) in the multi-kernel path; a.scratch holds
+// scratch_bytes_fc_f64 bytes.
+hipError_t launch_step_fc_f64(const StepArgs& a);
+size_t scratch_bytes_fc_f64(int nx, int ny);
 hipError_t launch_adjoint_f64(const StepArgs& a, const void* const cot1[16], void* const cot0[16]);
 size_t scratch_bytes_adjoint_f64(int nx, int ny);
 // Allocation-free adjoint: the scratch lives in a static device array of fixed size

@@ -106,13 +106,15 @@ AF_HD void locate(T off, T o, int& cell, T& xi, unsigned& st) {
 // F_EH) at (i, j) for duration tau = lam h (Sec. 6.1 steps 3-4).  The family may be
 // a run-time value (lanes of one wavefront then share one instruction stream) or a
 // constant (point_update<FAM, ...>).
-template <int SCHEME, class T, class A, class D, class Pol>
-AF_HD Prim<T> point_update_f(const A& acc, const D& dinc, int fam, int i, int j, const Pol& pol, T lam,
-                             unsigned& st) {
+// The convective foot of the target of family fam at (i, j) (node value WP) after
+// tau = lam h, by the two Picard stages (eq. adv-footpoint; Sec. 6.1 step 3): the
+// foot's cell (ci, cj) and its local coordinates (xi, eta) in [-1, 1].
+template <class T, class A, class Pol>
+AF_HD void picard_foot(const A& acc, int fam, int i, int j, const Pol& pol, T lam, const Prim<T>& WP, int& ci,
+                       int& cj, T& xi, T& eta, unsigned& st) {
     const T ox = fam_ox<T>(fam), oy = fam_oy<T>(fam);
-    Prim<T> WP = acc.node(fam, i, j);
     int cx, cy;
-    T xi, eta, xm, xp, ym, yp;
+    T xm, xp, ym, yp;
     // first Picard step: at a node the reconstruction equals the node value
     locate(ox - lam * pol.vu(WP.u), ox, cx, xi, st);
     locate(oy - lam * pol.vv(WP.v), oy, cy, eta, st);
@@ -131,10 +133,20 @@ AF_HD Prim<T> point_update_f(const A& acc, const D& dinc, int fam, int i, int j,
     // second Picard step from P with the velocity at the first foot
     locate(ox - lam * pol.vu(u1), ox, cx, xi, st);
     locate(oy - lam * pol.vv(v1), oy, cy, eta, st);
+    ci = i + cx;
+    cj = j + cy;
+}
+
+template <int SCHEME, class T, class A, class D, class Pol>
+AF_HD Prim<T> point_update_f(const A& acc, const D& dinc, int fam, int i, int j, const Pol& pol, T lam,
+                             unsigned& st) {
+    Prim<T> WP = acc.node(fam, i, j);
+    int ci, cj;
+    T xi, eta, xm, xp, ym, yp;
+    picard_foot(acc, fam, i, j, pol, lam, WP, ci, cj, xi, eta, st);
     lag_pm(xi, xm, xp);
     lag_pm(eta, ym, yp);
-    const int ci = i + cx, cj = j + cy;
-    T fr[3][3], fp[3][3];
+    T fr[3][3], fu[3][3], fv[3][3], fp[3][3];
     {
         Prim<T> n[3][3];
         cell_nodes<T>(acc, ci, cj, n);

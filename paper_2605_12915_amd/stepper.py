@@ -13,7 +13,7 @@ from typing import Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import AF_CHECK, AF_F32, AF_F64, AF_SCHEME_RB, AfConfig, AfDiag, AfState, check
+from ._lib import AF_CHECK, AF_F32, AF_F64, AF_SCHEME_RB, SCHEME_FLAGS, AfConfig, AfDiag, AfState, check
 
 
 def state_struct(t: torch.Tensor) -> AfState:
@@ -47,7 +47,9 @@ class Stepper:
         cfg.precision = AF_F64 if precision == "f64" else AF_F32
         for k in range(4):
             cfg.bg[k] = float(bg[k])
-        cfg.flags = (AF_CHECK if check_errors else 0) | (AF_SCHEME_RB if scheme == "rb" else 0)
+        if scheme not in SCHEME_FLAGS:
+            raise ValueError(f"scheme must be one of {sorted(SCHEME_FLAGS)}")
+        cfg.flags = (AF_CHECK if check_errors else 0) | SCHEME_FLAGS[scheme]
         self.cfg = cfg
         self.dtype = torch.float64 if precision == "f64" else torch.float32
         self._last_out = None      # FP32: the tensor holding the output the compensation belongs to

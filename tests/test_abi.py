@@ -55,9 +55,25 @@ def test_bad_config_rejected_on_host(L):
 
 def test_status_strings(L):
     from paper_2605_12915_amd import _lib
-    for code in range(7):
-        assert L.af_status_string(code)
+    for code in range(_lib.AF_ERR_FOOTPRINT + 1):
+        assert L.af_status_string(code) != b"unknown status"
     assert b"CFL" in L.af_status_string(_lib.AF_ERR_ACOUSTIC_CFL)
+    assert b"footprint" in L.af_status_string(_lib.AF_ERR_FOOTPRINT)
+
+
+def test_footcentred_config_rules_on_host(L):
+    """AF_SCHEME_FC: FP64 single-grid only and not with AF_SCHEME_RB (refused by af_init
+    before any device work)."""
+    from paper_2605_12915_amd import _lib
+    cfg = _lib.AfConfig()
+    cfg.nx, cfg.ny, cfg.h, cfg.gamma, cfg.precision = 8, 8, 0.125, 1.4, _lib.AF_F64
+    cfg.flags = _lib.AF_SCHEME_FC | _lib.AF_SCHEME_RB
+    ctx = ctypes.c_void_p()
+    assert L.af_init(ctypes.byref(cfg), None, ctypes.byref(ctx)) == _lib.AF_ERR_ARG
+    cfg.flags = _lib.AF_SCHEME_FC
+    cfg.precision = _lib.AF_F32
+    cfg.bg[0], cfg.bg[3] = 1.0, 1.0
+    assert L.af_init(ctypes.byref(cfg), None, ctypes.byref(ctx)) == _lib.AF_ERR_UNSUPPORTED
 
 
 def test_bad_batch_config_rejected_on_host(L):
