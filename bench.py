@@ -12,8 +12,10 @@ The same run measures the three forms built on the step (in "forms"):
            of an annulus acoustic energy through 200 steps (checkpoints every 20)
            and its central finite-difference check in 8 density directions;
   batch    64 double shear layers of seeded sizes N in [32, 1024], 1000 FP32 steps
-           in one hipGraph of persistent launches; aggregate rate, tuning table and
-           per-size-class rates.
+           in one hipGraph (one launch per step; tile shape and grid mode autotuned);
+           aggregate rate, tuning table, per-size-class rates, error against FP64;
+  fc       the foot-centred exact point update (App. C) on the 256^2 Fourier-mode
+           flow: step rate, its cost against the transported step at the same size.
 
 Prints ONE JSON line; progress goes to stderr.
 """
@@ -44,7 +46,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=2048)
-    ap.add_argument("--forms", default="fp32,adjoint,batch",
+    ap.add_argument("--fc-n", type=int, default=256)
+    ap.add_argument("--fc-steps", type=int, default=3)
+    ap.add_argument("--forms", default="fp32,adjoint,batch,fc",
                     help="comma list of forms to measure after the headline (or 'none')")
     ap.add_argument("--fp32-n", type=int, default=4096)
     ap.add_argument("--fp32-steps", type=int, default=500)
@@ -400,6 +404,50 @@ def form_batch(torch, dev, count, steps, big_fp32_rate, lite=False):
     return out
 
 
+def form_fc(torch, dev, n, steps):
+    """The foot-centred exact point update (AF_SCHEME_FC, App. C) against the
+    transported update on the same n^2 Fourier-mode flow (the headline's workload at a
+    smaller size): HIP-event kernel times of the point kernel and of the transported
+    step, their ratio (the paper estimates about a thousand), and the executed-FP64
+    roofline of the point kernel from its stored counters (its flops depend on how
+    many grid lines cut each disk)."""
+    from paper_2605_12915_amd import inputs as I
+    from paper_2605_12915_amd import perf
+    from paper_2605_12915_amd.stepper import Stepper
+    P = I.fourier_modes(n)
+    dt = P.dt_for_cfl(0.4)
+    x = torch.from_numpy(P.state()).to(dev)
+    out = {"nx": n, "ny": n, "steps": steps, "dt": dt, "workload": f"periodic {n}x{n} FP64 Fourier-mode flow, CFL 0.4"}
+    for scheme, k in (("fc", steps), ("tai", 50)):
+        st = Stepper(n, n, P.h, P.gamma, scheme=scheme, device=dev, check_errors=True)
+        st.time_steps(x, dt, 1)
+        tot, ker = st.time_steps(x, dt, k)
+        out[f"{scheme}_step_ms"] = tot / k
+        out[f"{scheme}_kernel_ms"] = ker
+        if scheme == "fc":
+            kname = st.dominant_kernel()
+            y = x.clone()
+            st.step(y, dt, 1)
+            out["status"] = st.read_status()
+            out["finite"] = bool(torch.isfinite(y).all())
+        st.close()
+    out["value"] = n * n / (out["fc_step_ms"] * 1e-3) / 1e6
+    out["unit"] = "Mcell-updates/s"
+    out["fc_over_tai_kernel"] = out["fc_kernel_ms"] / out["tai_kernel_ms"]
+    out["fc_over_tai_step"] = out["fc_step_ms"] / out["tai_step_ms"]
+    roof = {"bound": "alu", "peak": perf.FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "kernel": kname,
+            "kernel_ms": out["fc_kernel_ms"], "achieved": None, "frac": None, "traffic": None,
+            "achieved_kind": "executed FP64 flops of the point kernel (SQ_INSTS_VALU_FLOPS_FP64 x 64) per launch"}
+    tr = perf.stored_traffic(kname)
+    if tr and tr.get("cells_per_launch") == n * n and tr.get("executed_fp64_flops_per_launch"):
+        ach = tr["executed_fp64_flops_per_launch"] / (out["fc_kernel_ms"] * 1e-3) / 1e12
+        roof.update({"achieved": ach, "frac": ach / perf.FP64_PEAK_TFLOPS, "traffic": tr["traffic_bytes_per_launch"],
+                     "executed_flops_per_cell": tr["executed_fp64_flops_per_launch"] / (n * n)})
+    out["roofline"] = roof
+    log(f"fc: {out['value']:.1f} Mcell/s, {out['fc_over_tai_kernel']:.0f}x the transported kernel")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -499,6 +547,8 @@ def main():
         line["forms"]["adjoint"] = form_adjoint(torch, dev, args.adj_n, args.adj_steps, ndir=args.adj_dirs)
     if "batch" in forms:
         line["forms"]["batch"] = form_batch(torch, dev, args.batch_count, args.batch_steps, big32, lite=args.batch_lite)
+    if "fc" in forms:
+        line["forms"]["fc"] = form_fc(torch, dev, args.fc_n, args.fc_steps)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         if args.cpu_sample_n:

@@ -170,10 +170,10 @@ AF_HD void fc_disk(const A& acc, int i, int j, double Xf, double Yf, double R, c
                         C.v[a][b] = n[a][b].v - ws.v;
                     }
             }
+#pragma unroll 1
             for (int k = 0; k < 32; ++k) {
-                const double sk = kGaussX32[k];
-                const double th = t0 + 0.5 * (t1 - t0) * (1.0 - cos(kFcPi * sk));
-                const double wth = kGaussW32[k] * 0.5 * (t1 - t0) * kFcPi * sin(kFcPi * sk);
+                const double th = t0 + 0.5 * (t1 - t0) * (1.0 - kGaussCos32[k]);
+                const double wth = kGaussW32[k] * 0.5 * (t1 - t0) * kFcPi * kGaussSin32[k];
                 const double ct = cos(th), st = sin(th);
                 auto psi_at = [&](int c) -> double {
                     const double qv = axis[c] == 0 ? lam / ct : mu / st;
@@ -181,11 +181,11 @@ AF_HD void fc_disk(const A& acc, int i, int j, double Xf, double Yf, double R, c
                 };
                 const double p0 = seg == 0 ? 0.0 : psi_at(seg - 1);
                 const double p1 = seg == nx_ ? 0.5 * kFcPi : psi_at(seg);
+                const bool whole = nx_ == 0;   // psi over [0, pi/2]: tabulated sines
 #pragma unroll 2
                 for (int m = 0; m < 10; ++m) {
-                    const double ps = p0 + (p1 - p0) * kGaussX10[m];
                     const double wps = (p1 - p0) * kGaussW10[m];
-                    const double rho = sin(ps);
+                    const double rho = whole ? kGaussSinHalf10[m] : sin(p0 + (p1 - p0) * kGaussX10[m]);
                     const double zx = rho * ct, zy = rho * st;
                     const double X = Xf + R * zx, Y = Yf + R * zy;
                     fc_point(C, 2.0 * (X - cx) - 1.0, 2.0 * (Y - cy) - 1.0, zx, zy, ct, st,

@@ -51,6 +51,8 @@ KERNEL_SOURCES = {
     "af::k_fused<float, af::PolPert<float>, 31, 10, 512, 0, true, 4, 32, true>": ["csrc/af_fused_f32.hip"] + _STEP,
     "af::k_fused_batch_direct<31, 10, 512, 4, 0, 32>": ["csrc/af_batch.hip", "csrc/af_batch.h"] + _STEP,
     **{k: _ADJ for k in ADJOINT_KERNELS},
+    "af::k_fc_points": ["csrc/af_f64.hip", "csrc/af_footcentred.h", "csrc/af_gauss.h", "csrc/af_kernels.h",
+                        "csrc/af_device.h", "csrc/af_blocks.h", "csrc/af_internal.h", "build.py"],
 }
 
 
