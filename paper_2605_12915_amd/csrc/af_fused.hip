@@ -28,7 +28,7 @@ namespace af {
 // staged arrays 36 words; phase 2 has 34x13 = 442 node-cells (one round) and phase 3
 // places every target family in rows of 32 lanes: 32x11 V, 32x10 Ev and 31(+1)x11 Eh
 // targets fill exactly two rounds of 512, and a half-wavefront (the lanes the LDS
-// serves together) always reads 16 consecutive words.  The family is a run-time value
+// serves together) reads one row of 32 consecutive doubles (all 64 banks).  The family is a run-time value
 // in phase 3 (DYN), so the two wavefronts that hold targets of two families run one
 // instruction stream.  Measured at 2048^2 against the earlier 26x12 tile with tight
 // item rows and the family as a template constant (1.030 ms): the run-time family

@@ -16,7 +16,9 @@ namespace af {
 // lanes with the run-time family, as in the FP64 kernel.  Measured at 4096^2 against
 // the earlier 24x13 tile with tight rows and the family as a template constant
 // (2.061 ms): the run-time family alone 1.994 ms, the 31x10 rows with the constant
-// family 1.953 ms, both 1.905 ms; all four give identical bits.
+// family 1.953 ms, both 1.905 ms; all four give identical bits.  Then the phase-2
+// family fence (no more scratch traffic from spills) 1.826 ms and the FP64 row layout
+// of the staged arrays (bank conflicts cut eightfold) 1.742 ms, identical bits.
 constexpr int kFTX = 31, kFTY = 10, kFNT = 512, kFMinW = 4, kFRW = 32;
 
 PolPert<float> pert_pol_f32(const double bg[4], double g) {

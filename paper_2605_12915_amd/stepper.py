@@ -138,8 +138,10 @@ class Stepper:
 
 class Batch:
     """Batching form: many FP32 perturbation grids (uneven sizes, each with its own h,
-    gamma, background and dt) stepped together, one persistent launch per step, the
-    nsteps launches replayed from a hipGraph (af_init_batch / af_step_batch)."""
+    gamma, background and dt) stepped together, one launch per step over all grids
+    (tile shape and grid mode, persistent or one workgroup per tile, chosen by the
+    library's autotuner), the nsteps launches replayed from a hipGraph (af_init_batch /
+    af_step_batch)."""
 
     def __init__(self, grids: Sequence[dict], check_errors: bool = False, scheme: str = "tai",
                  stream: Optional[torch.cuda.Stream] = None, device: Optional[torch.device] = None):

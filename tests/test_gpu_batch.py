@@ -1,5 +1,5 @@
-"""Batching form (af_init_batch / af_step_batch): many uneven FP32 grids in one
-persistent launch per step, replayed from a hipGraph.
+"""Batching form (af_init_batch / af_step_batch): many uneven FP32 grids in one launch
+per step (tile shape and grid mode autotuned), replayed from a hipGraph.
 
 * every tile configuration against the single-grid FP32 path, instance by instance
   (same arithmetic per cell, so the results must agree bit for bit);
