@@ -23,6 +23,7 @@ MI355X peaks: HBM3E 8.0 TB/s; FP64 vector 78.6 TFLOP/s (256 CUs x 4 SIMDs x
 from __future__ import annotations
 
 import hashlib
+import re
 import json
 import os
 
@@ -56,14 +57,28 @@ KERNEL_SOURCES = {
 }
 
 
+def _code_of(path: str) -> bytes:
+    """A source file without its comments and with whitespace runs collapsed, so that
+    edits of comments alone do not mark stored counters as stale (C/C++ // and /* */
+    comments; # comments in Python files)."""
+    with open(path, encoding="utf-8") as fh:
+        text = fh.read()
+    if path.endswith(".py"):
+        text = re.sub(r"(?m)^\s*#.*$", "", text)
+    else:
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+    return " ".join(text.split()).encode()
+
+
 def source_sha(kernel: str) -> str | None:
+    """Hash of the code (comments stripped) of the files a kernel is built from."""
     files = KERNEL_SOURCES.get(kernel)
     if not files:
         return None
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(HERE, f), "rb") as fh:
-            h.update(fh.read())
+        h.update(_code_of(os.path.join(HERE, f)))
     return h.hexdigest()[:16]
 
 
