@@ -4,11 +4,12 @@
 // (count_flops.cpp, an operation-counting scalar) run the very same code.
 //
 // Accessors:
-//   S  staged forward state: S.at(plane, base, off) with the window plane numbering
-//      (0..11 point values fam * 4 + (rho, u, v, p), 12..15 recovered centres,
-//      16..39 increments tau * 12 + fam * 3 + (u, v, p)); S_::kRX, S_::kPlane.
-//   O  scatter target with the same numbering: O.base(i, j), O.addb(plane, base,
-//      off, value), O.node(fam, i, j, g[4]); every add is one accumulation.
+//   S  staged forward state: S.base(i, j), S.at(plane, base, off) with the window
+//      plane numbering (0..11 point values fam * 4 + (rho, u, v, p), 12..15 recovered
+//      centres, 16..39 increments tau * 12 + fam * 3 + (u, v, p)); row stride S_::kRX.
+//   O  scatter target with the same plane numbering (its own row stride O_::kRX):
+//      O.base(i, j), O.addb(plane, base, off, value), O.node(fam, i, j, g[4]); every
+//      add is one accumulation.
 //   A  forward nodes by cell: A.node(fam, i, j) (fam = F_C: recovered centre).
 //   CT cotangent of the step's output: CT.get(plane, i, j) (periodic).
 //   LD cotangent of the increments: LD.get(tau * 12 + fam * 3 + q, i, j).
@@ -79,8 +80,7 @@ template <int FAM, int SCHEME, int MODE, class T, class S_, class O_>
 AF_HD bool point_update_adj(const S_& S, const O_& O, int t, int i, int j, const Prim<T>& WP, T gamma, T lam,
                             const T nuF[4], const T nuG[4], T ws, const T* extra, T gself[4]) {
     const T ox = T(FamOffset<FAM>::ox), oy = T(FamOffset<FAM>::oy);
-    constexpr int RX = O_::kRX;
-    static_assert(S_::kRX == O_::kRX && S_::kPlane == O_::kPlane, "staged state and window share a layout");
+    constexpr int RX = O_::kRX, SRX = S_::kRX;   // row strides of the window and of the staged state
     unsigned st = 0;
     // ---- forward recomputation ----
     int cx1, cy1, cx2, cy2;
@@ -92,14 +92,14 @@ AF_HD bool point_update_adj(const S_& S, const O_& O, int t, int i, int j, const
     lagr(eta1, ly1, dly1);
     T u1 = T(0), v1 = T(0), du1x = T(0), du1y = T(0), dv1x = T(0), dv1y = T(0);
     T w1[3][3];   // tensor weights of the first foot (reused by the reverse scatter)
-    const int wb1 = O.base(i + cx1, j + cy1);
+    const int wb1 = O.base(i + cx1, j + cy1), sb1 = S.base(i + cx1, j + cy1);
     {
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                const int f = fam_of(a, b), off = (b == 2 ? RX : 0) + (a == 2 ? 1 : 0);
-                const T nu_ = S.at(win_plane(f) + 1, wb1, off), nv_ = S.at(win_plane(f) + 2, wb1, off);
+                const int f = fam_of(a, b), soff = (b == 2 ? SRX : 0) + (a == 2 ? 1 : 0);
+                const T nu_ = S.at(win_plane(f) + 1, sb1, soff), nv_ = S.at(win_plane(f) + 2, sb1, soff);
                 const T w = lx1[a] * ly1[b], wx = dlx1[a] * ly1[b], wy = lx1[a] * dly1[b];
                 w1[a][b] = w;
                 u1 += w * nu_;
@@ -119,7 +119,7 @@ AF_HD bool point_update_adj(const S_& S, const O_& O, int t, int i, int j, const
     T Wf[4] = {T(0), T(0), T(0), T(0)}, dWx[4] = {T(0), T(0), T(0), T(0)}, dWy[4] = {T(0), T(0), T(0), T(0)};
     T Df[3] = {T(0), T(0), T(0)}, dDx[3] = {T(0), T(0), T(0)}, dDy[3] = {T(0), T(0), T(0)};
     T w2[3][3];   // tensor weights of the second foot (reused by the reverse scatter)
-    const int wb2 = O.base(ci, cj);
+    const int wb2 = O.base(ci, cj), sb2 = S.base(ci, cj);
     {
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -127,16 +127,16 @@ AF_HD bool point_update_adj(const S_& S, const O_& O, int t, int i, int j, const
             for (int b = 0; b < 3; ++b) {
                 const T w = lx2[a] * ly2[b], wx = dlx2[a] * ly2[b], wy = lx2[a] * dly2[b];
                 w2[a][b] = w;
-                const int f = fam_of(a, b), off = (b == 2 ? RX : 0) + (a == 2 ? 1 : 0);
+                const int f = fam_of(a, b), soff = (b == 2 ? SRX : 0) + (a == 2 ? 1 : 0);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const T v = S.at(win_plane(f) + q, wb2, off);
+                    const T v = S.at(win_plane(f) + q, sb2, soff);
                     Wf[q] += w * v; dWx[q] += wx * v; dWy[q] += wy * v;
                 }
                 if constexpr (SCHEME == 0) {
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
-                        const T v = S.at(16 + t * 12 + f * 3 + q, wb2, off);
+                        const T v = S.at(16 + t * 12 + f * 3 + q, sb2, soff);
                         Df[q] += w * v; dDx[q] += wx * v; dDy[q] += wy * v;
                     }
                 }
@@ -144,8 +144,9 @@ AF_HD bool point_update_adj(const S_& S, const O_& O, int t, int i, int j, const
     }
     const int wbP = O.base(i, j);
     if constexpr (SCHEME == 1) {
+        const int sbP = S.base(i, j);
 #pragma unroll
-        for (int q = 0; q < 3; ++q) Df[q] = S.at(16 + t * 12 + FAM * 3 + q, wbP, 0);
+        for (int q = 0; q < 3; ++q) Df[q] = S.at(16 + t * 12 + FAM * 3 + q, sbP, 0);
     }
     // ---- reverse ----
     // compose: rho = rho_f + dp rho_K / (gamma p_K), u = u_f + du, v = v_f + dv, p = p_f + dp,
@@ -264,9 +265,9 @@ AF_HD unsigned point_adj_target(const S_& S, const CT& cot1, const O_& O, int i,
             nuG[k] = muG_ij * T(4.0 / 6.0);
         }
     }
-    const int wb = O.base(i, j);
+    const int wb = O.base(i, j), sb = S.base(i, j);
     const int pl = win_plane(FAM);
-    const Prim<T> w0{S.at(pl, wb, 0), S.at(pl + 1, wb, 0), S.at(pl + 2, wb, 0), S.at(pl + 3, wb, 0)};
+    const Prim<T> w0{S.at(pl, sb, 0), S.at(pl + 1, sb, 0), S.at(pl + 2, sb, 0), S.at(pl + 3, sb, 0)};
     T g[4] = {T(0), T(0), T(0), T(0)};
     if constexpr (MODE == 1) {
         if (fix & 1u)

@@ -291,13 +291,19 @@ __global__ void __launch_bounds__(kFNT, 2) k_adj_fwd(StatePtrs<double> prim, dou
 // [-1, B + 2) of the block: the block stages the forward state of that window in LDS
 // (each thread loads all 40 planes of one node-cell at once) and accumulates into an
 // LDS window of the same shape.
-// 8x8 blocks: the staged state and the window take 77 KB, so two blocks share a CU and
+// 8x8 blocks: the staged state and the window take 79 KB, so two blocks share a CU and
 // one's staging overlaps the other's work (2% faster than 16x8 at one block per CU,
 // despite the larger window overlap, 1.89x against 1.63x).
+// The accumulation window's rows are padded to WX = 12 doubles (its twelfth column is
+// never written): with the block's rows split between the half-wavefronts as
+// {0, 2, 4, 6} and {1, 3, 5, 7}, the four rows a half-wavefront adds to at a common
+// offset start 0, 24, 48 and 72 doubles apart, i.e. in four distinct quarters of the
+// 64 LDS banks (with 11-double rows, rows 0 and 3 of four consecutive ones collide).
 template <int BX, int BY>
 struct PointBlock {
     static constexpr int NT = 3 * BX * BY, RX = BX + 3, RY = BY + 3, WIN = RX * RY;
-    static constexpr size_t LDS = sizeof(double) * 2 * 40 * WIN;   // staged state + accumulators
+    static constexpr int WX = BX == 8 ? 12 : RX, WWIN = WX * RY;
+    static constexpr size_t LDS = sizeof(double) * 40 * (WIN + WWIN);   // staged state + accumulators
     static_assert(WIN <= NT, "one staging round");
     static_assert((BX * BY) % 64 == 0, "each wavefront holds one target family");
 };
@@ -314,7 +320,7 @@ __global__ void __launch_bounds__(3 * BX * BY, MINB)
     double* stage = reinterpret_cast<double*>(smem);   // [40][RY][RX]
     const int tile = xcd_tile(blockIdx.x, ntiles);
     const int i0 = (tile % tiles_x) * BX, j0 = (tile / tiles_x) * BY;
-    const LdsWin<40, B::RX, B::RY> O{stage + 40 * B::WIN, i0 - 1, j0 - 1};
+    const LdsWin<40, B::WX, B::RY> O{stage + 40 * B::WIN, i0 - 1, j0 - 1};
     O.zero();
     if (threadIdx.x < B::WIN) {
         const int e = threadIdx.x;
@@ -333,7 +339,9 @@ __global__ void __launch_bounds__(3 * BX * BY, MINB)
     __syncthreads();
     const StageWin<B::RX, B::RY> S{stage, i0 - 1, j0 - 1};
     const int cell = (int)threadIdx.x % (BX * BY), fam = (int)threadIdx.x / (BX * BY);   // wave-uniform
-    const int i = i0 + cell % BX, j = j0 + cell / BX;
+    // rows of a half-wavefront: even rows in the first, odd rows in the second (8x8)
+    const int row = BX == 8 && BY == 8 ? 2 * ((cell / 8) % 4) + cell / 32 : cell / BX;
+    const int i = i0 + cell % BX, j = j0 + row;
     if (i < nx && j < ny) {
         const CotAcc C1{cot1, nx, ny};
         unsigned fix;

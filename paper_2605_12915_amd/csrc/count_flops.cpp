@@ -74,6 +74,7 @@ constexpr int kWX = 8;
 struct HostStage {
     static constexpr int kRX = kWX, kPlane = kWX * kWX;
     Cnt a[40 * kWX * kWX];
+    int base(int i, int j) const { return (j + 2) * kWX + (i + 2); }
     Cnt at(int pl, int b, int off) const { return a[b + pl * kPlane + off]; }
 };
 struct HostWin {
