@@ -341,38 +341,54 @@ class FootprintError(RuntimeError):
     """The disk about a foot leaves the compact footprint of eq. fc-half-footprint."""
 
 
-def point_values(state, h, gamma, tau, closure="linear", check=True):
-    """New point values (12, ny, nx) of all targets after tau by the foot-centred exact
-    frozen-acoustic update; state absolute FP64 (16, ny, nx)."""
+def _prepare(state, h, gamma, tau):
     state = np.ascontiguousarray(state, float)
-    _, ny, nx = state.shape
     C = ref.centres(state, h, gamma)
     feet, _, st = ref.feet(state, h, gamma, tau)
     if st == 2:
         raise FootprintError("a foot moved one cell or more")
     W = [Q2Lattice.of_state(state, C, k) for k in range(4)]
+    return feet, W
+
+
+def _target_value(feet, W, h, gamma, tau, fam, i, j, closure, check):
+    """New point value (rho, u, v, p) of the target of family fam at (i, j)."""
+    ox, oy = FAM_OFFSET[fam]
+    dx, dy = feet[fam, 0, j, i], feet[fam, 1, j, i]
+    Fx, Fy = i + ox + dx, j + oy + dy
+    rho_s, u_s, v_s, p_s = (float(W[k].eval(np.array(Fx), np.array(Fy))) for k in range(4))
+    c_s = math.sqrt(gamma * p_s / rho_s)
+    Z_s = rho_s * c_s
+    R = c_s * tau / h
+    if check and (abs(dx) + R >= 0.5 or abs(dy) + R >= 0.5):
+        raise FootprintError(f"target {fam} ({i}, {j}): |delta| + R >= h/2")
+    fpi = Q2Lattice(W[3].n / Z_s)
+    pi_a, u_a, v_a = exact_acoustic((Fx, Fy), R, fpi, W[1], W[2])
+    p_a = Z_s * pi_a
+    if closure == "linear":
+        rho_a = rho_s + (p_a - p_s) / (c_s * c_s)
+    else:
+        rho_a = rho_s * (p_a / p_s) ** (1.0 / gamma)
+    return np.array([rho_a, u_a, v_a, p_a])
+
+
+def point_values(state, h, gamma, tau, closure="linear", check=True):
+    """New point values (12, ny, nx) of all targets after tau by the foot-centred exact
+    frozen-acoustic update; state absolute FP64 (16, ny, nx)."""
+    _, ny, nx = np.shape(state)
+    feet, W = _prepare(state, h, gamma, tau)
     out = np.empty((12, ny, nx))
     for fam in range(3):
-        ox, oy = FAM_OFFSET[fam]
         for j in range(ny):
             for i in range(nx):
-                dx, dy = feet[fam, 0, j, i], feet[fam, 1, j, i]
-                Fx, Fy = i + ox + dx, j + oy + dy
-                rho_s, u_s, v_s, p_s = (float(W[k].eval(np.array(Fx), np.array(Fy))) for k in range(4))
-                c_s = math.sqrt(gamma * p_s / rho_s)
-                Z_s = rho_s * c_s
-                R = c_s * tau / h
-                if check and (abs(dx) + R >= 0.5 or abs(dy) + R >= 0.5):
-                    raise FootprintError(f"target {fam} ({i}, {j}): |delta| + R >= h/2")
-                fpi = Q2Lattice(W[3].n / Z_s)
-                pi_a, u_a, v_a = exact_acoustic((Fx, Fy), R, fpi, W[1], W[2])
-                p_a = Z_s * pi_a
-                if closure == "linear":
-                    rho_a = rho_s + (p_a - p_s) / (c_s * c_s)
-                else:
-                    rho_a = rho_s * (p_a / p_s) ** (1.0 / gamma)
-                out[4 * fam:4 * fam + 4, j, i] = (rho_a, u_a, v_a, p_a)
+                out[4 * fam:4 * fam + 4, j, i] = _target_value(feet, W, h, gamma, tau, fam, i, j, closure, check)
     return out
+
+
+def point_values_at(state, h, gamma, tau, targets, closure="linear", check=True):
+    """The same for a list of targets (fam, i, j) only: an array (len(targets), 4)."""
+    feet, W = _prepare(state, h, gamma, tau)
+    return np.array([_target_value(feet, W, h, gamma, tau, f, i, j, closure, check) for f, i, j in targets])
 
 
 def _flux_x(W, g):

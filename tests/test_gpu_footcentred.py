@@ -114,3 +114,44 @@ def test_fc_unsupported_combinations(torch_dev):
         st.adjoint(x, x.clone(), P.dt_for_cfl(0.3))
     assert e.value.code == AF_ERR_UNSUPPORTED
     assert st.dominant_kernel() == "af::k_fc_points"
+
+
+def test_fc_benchmark_size_sampled(torch_dev):
+    """The benchmark's 256^2 Fourier-mode flow at CFL 0.4, one step: the new point values
+    of 30 random targets against the oracle's, target by target, and the averages of 6
+    random cells against the oracle's update from the oracle's half- and full-step values
+    of the eight targets each cell's edge fluxes use."""
+    P = I.fourier_modes(256)
+    s0 = P.state()
+    dt = P.dt_for_cfl(0.4)
+    got = _gpu(torch_dev, P, s0, dt, 1, check_errors=True)
+    n = P.nx
+    rng = np.random.default_rng(17)
+    targets = [(int(f), int(i), int(j)) for f, i, j in zip(rng.integers(0, 3, 30), rng.integers(0, n, 30),
+                                                           rng.integers(0, n, 30))]
+    want = fc.point_values_at(s0, P.h, P.gamma, dt, targets)
+    for (f, i, j), w in zip(targets, want):
+        g = got[4 + 4 * f:8 + 4 * f, j, i]
+        assert np.abs(g - w).max() <= TOL * max(1.0, np.abs(w).max()), ((f, i, j), g, w)
+    # averages of sampled cells (periodic neighbours)
+    gam = P.gamma
+    cells = [(int(i), int(j)) for i, j in zip(rng.integers(0, n, 6), rng.integers(0, n, 6))]
+    for i, j in cells:
+        ip, jp = (i + 1) % n, (j + 1) % n
+        need = [(0, i, j), (0, ip, j), (0, i, jp), (0, ip, jp), (1, i, j), (1, ip, j), (2, i, j), (2, i, jp)]
+        half = fc.point_values_at(s0, P.h, gam, 0.5 * dt, need)
+        full = fc.point_values_at(s0, P.h, gam, dt, need)
+        now = np.array([s0[4 + 4 * f:8 + 4 * f, b, a] for f, a, b in need])
+        tf = lambda fl, k: (fl(now[k], gam) + 4.0 * fl(half[k], gam) + fl(full[k], gam)) / 6.0
+        FV = {k: tf(fc._flux_x, k) for k in range(4)}
+        GV = {k: tf(fc._flux_y, k) for k in range(4)}
+        FE = {k: tf(fc._flux_x, k) for k in (4, 5)}
+        GE = {k: tf(fc._flux_y, k) for k in (6, 7)}
+        Fl = (FV[0] + 4.0 * FE[4] + FV[2]) / 6.0
+        Fr = (FV[1] + 4.0 * FE[5] + FV[3]) / 6.0
+        Gb = (GV[0] + 4.0 * GE[6] + GV[1]) / 6.0
+        Gt = (GV[2] + 4.0 * GE[7] + GV[3]) / 6.0
+        want_avg = s0[0:4, j, i] - dt / P.h * ((Fr - Fl) + (Gt - Gb))
+        g = got[0:4, j, i]
+        assert np.abs(g - want_avg).max() <= TOL * np.abs(want_avg).max(), ((i, j), g, want_avg)
+
