@@ -80,7 +80,7 @@ def run_f32_scheme(torch_dev, P, s0, dt, n, bg, scheme):
     return from_perturbation(x.cpu().numpy(), bg, P.gamma)
 
 
-@pytest.mark.parametrize("nx,ny", [(37, 29), (70, 9)])
+@pytest.mark.parametrize("nx,ny", [(37, 29), (70, 9), (9, 70), (62, 20)])
 def test_f32_ragged_and_rb(torch_dev, orc, nx, ny):
     """Ragged grids, both point updates: the transported update (TAI) and the additive
     RB update against the oracle's RB step (scheme 1) at the RB's stable CFL."""

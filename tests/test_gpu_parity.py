@@ -50,7 +50,8 @@ def test_vortex_64_100_steps(torch_dev, orc):
     assert err.max() <= TOL, err
 
 
-@pytest.mark.parametrize("nx,ny,steps", [(4, 4, 5), (5, 7, 4), (37, 29, 6), (70, 9, 3)])
+@pytest.mark.parametrize("nx,ny,steps", [(4, 4, 5), (5, 7, 4), (37, 29, 6), (70, 9, 3), (9, 70, 3), (31, 10, 4),
+                                         (62, 20, 4), (12, 200, 2), (200, 12, 2)])
 def test_ragged_and_small_grids(torch_dev, orc, nx, ny, steps):
     P = I.random_smooth(nx, ny, seed=nx * 100 + ny, amp=0.1, vel=(0.35, -0.25))
     s0 = P.state()
