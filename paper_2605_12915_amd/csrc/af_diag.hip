@@ -64,10 +64,11 @@ struct DiagAcc {
     }
 };
 
-// Registers capped for 4 waves per SIMD (a few dwords spill): 15% faster than the
-// free allocation (208 registers, 2 waves per SIMD) once the vorticity terms are in.
+// Two waves per SIMD (181 registers, no spill).  With the logarithm of af_math.h the
+// 4-wave cap that suited the library's logarithm (5 dwords spilled then, 0.29 ms per call
+// at 2048^2) spills 56 dwords (0.73 ms) and a 3-wave cap 14 (0.30 ms); 0.23 ms here.
 template <class T>
-__global__ void __launch_bounds__(kDiagBlock, 4) k_diag(StatePtrs<const T> st, int nx, int ny, double gamma,
+__global__ void __launch_bounds__(kDiagBlock, 2) k_diag(StatePtrs<const T> st, int nx, int ny, double gamma,
                                                      DiagBg bgs, double* partials) {
     __shared__ double sh[(kDiagBlock / 64) * kDiagVals];
     DiagAcc<T> A;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "af_internal.h"
+#include "af_math.h"
 
 namespace af {
 
@@ -46,7 +47,7 @@ __device__ __forceinline__ void diag_wave_reduce(double v[kDiagVals]) {
 // weighted by w, minima and maxima.
 __device__ __forceinline__ void diag_node(double v[kDiagVals], double w, double r, double u, double vv, double p,
                                           double gamma) {
-    v[4] -= w * r * (log(p) - gamma * log(r));
+    v[4] -= w * r * (log_pos(p) - gamma * log_pos(r));
     const double cs = sqrt(gamma * p / r);
     v[5] = fmin(v[5], r);
     v[6] = fmin(v[6], p);
