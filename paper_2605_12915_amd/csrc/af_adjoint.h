@@ -37,27 +37,30 @@ AF_HD void lagr(T s, T l[3], T dl[3]) {
 }
 
 // Flux Jacobians transposed: g += (dF/dW)^T nu, W = (rho, u, v, p).
-// (Each product shared by several terms is formed once, as the compiled code does.)
+// (Each product shared by several terms is formed once, as the compiled code does; the
+// one quotient, 1 / (gamma - 1), is the same in every call and formed once per thread.)
 template <class T>
 AF_HD void flux_x_T(const Prim<T>& w, T gamma, const T nu[4], T g[4]) {
+    const T gm1i = T(1) / (gamma - T(1));
     const T uu = w.u * w.u, uv = w.u * w.v, ru = w.r * w.u;
     const T q2 = T(0.5) * (uu + w.v * w.v);
-    const T E = w.p / (gamma - T(1)) + w.r * q2;
+    const T E = w.p * gm1i + w.r * q2;
     g[0] += nu[0] * w.u + nu[1] * uu + nu[2] * uv + nu[3] * w.u * q2;
     g[1] += nu[0] * w.r + nu[1] * T(2) * ru + nu[2] * w.r * w.v + nu[3] * (E + w.p + ru * w.u);
     g[2] += nu[2] * ru + nu[3] * ru * w.v;
-    g[3] += nu[1] + nu[3] * w.u * gamma / (gamma - T(1));
+    g[3] += nu[1] + nu[3] * w.u * gamma * gm1i;
 }
 
 template <class T>
 AF_HD void flux_y_T(const Prim<T>& w, T gamma, const T nu[4], T g[4]) {
+    const T gm1i = T(1) / (gamma - T(1));
     const T vv = w.v * w.v, uv = w.u * w.v, rv = w.r * w.v;
     const T q2 = T(0.5) * (w.u * w.u + vv);
-    const T E = w.p / (gamma - T(1)) + w.r * q2;
+    const T E = w.p * gm1i + w.r * q2;
     g[0] += nu[0] * w.v + nu[1] * uv + nu[2] * vv + nu[3] * w.v * q2;
     g[1] += nu[1] * rv + nu[3] * rv * w.u;
     g[2] += nu[0] * w.r + nu[1] * w.r * w.u + nu[2] * T(2) * rv + nu[3] * (E + w.p + rv * w.v);
-    g[3] += nu[2] + nu[3] * w.v * gamma / (gamma - T(1));
+    g[3] += nu[2] + nu[3] * w.v * gamma * gm1i;
 }
 
 // Transposed point update of target FAM at (i, j) for the duration tau = lam h;
@@ -180,13 +183,13 @@ AF_HD bool point_update_adj(const S_& S, const O_& O, int t, int i, int j, const
     const T ldq = lw[0] * Df[2] * qinv;
     if constexpr (SCHEME == 0) {
         lWf[0] = lw[0] + ldq;
-        lWf[3] = lw[3] - ldq * rK / pK;
+        lWf[3] = lw[3] - ldq * gamma * rq;   // rho_K / p_K = gamma rq
     } else {
         lWf[0] = lw[0];
         lWf[3] = lw[3];
         // the frozen rho_K / (gamma p_K) at the target, and its own increments
         gself[0] += ldq;
-        gself[3] -= ldq * rK / pK;
+        gself[3] -= ldq * gamma * rq;
 #pragma unroll
         for (int q = 0; q < 3; ++q) O.addb(16 + t * 12 + FAM * 3 + q, wbP, 0, lDf[q]);
     }
@@ -385,8 +388,10 @@ AF_HD void incr_adj(const A_& A, const LD_& LD, const O_& O, int i, int j, T gam
         }
     if (!any) return;
     const Prim<T> W = A.node(FAM, i, j);
-    const T c = sqrt(gamma * W.p / W.r);
-    const T Z = W.r * c, iZ = T(1) / Z;
+    // as in the forward freezing: 1 / Z = (gamma p rho)^(-1/2), c = gamma p / Z, Z = rho c
+    const T gp = gamma * W.p, q = gp * W.r;
+    const T iZ = rsqrt_of(q);
+    const T c = gp * iZ, Z = q * iZ;
     NodeAcc<T> na;
     na.zero();
     node_wedges<FAM>(A, i, j, na);
@@ -430,11 +435,13 @@ AF_HD void incr_adj(const A_& A, const LD_& LD, const O_& O, int i, int j, T gam
         lZ += l2r * s[1];
     }
     lZ += -iZ * iZ * liZ;
-    // c = sqrt(gamma p / rho), Z = rho c
+    // c = sqrt(gamma p / rho), Z = rho c: dc/drho = -c / (2 rho) = -c^2 / (2 Z),
+    // dc/dp = c / (2 p) = gamma / (2 Z), dZ/drho = c / 2, dZ/dp = Z / (2 p) = gamma rho / (2 Z)
     {
         const int wb = O.base(i, j);
-        O.addb(win_plane(FAM), wb, 0, lc * (-c / (T(2) * W.r)) + lZ * (T(0.5) * c));
-        O.addb(win_plane(FAM) + 3, wb, 0, lc * (c / (T(2) * W.p)) + lZ * (W.r * c / (T(2) * W.p)));
+        const T hiZ = T(0.5) * iZ;
+        O.addb(win_plane(FAM), wb, 0, lc * (-c * c * hiZ) + lZ * (T(0.5) * c));
+        O.addb(win_plane(FAM) + 3, wb, 0, lc * (gamma * hiZ) + lZ * (gamma * W.r * hiZ));
     }
     if constexpr (FAM == F_V) {
         wedge_adj<W_V_NE, 0, 0>(la, O, i, j);

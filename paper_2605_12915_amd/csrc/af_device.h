@@ -22,6 +22,24 @@
 
 namespace af {
 
+// 1 / sqrt(x): the device's reciprocal square root (one hardware estimate and its
+// refinement in FP64, the hardware instruction in FP32); the host builds that check
+// indexing and count operations take the plain quotient.
+AF_HD double rsqrt_of(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return rsqrt(x);
+#else
+    return 1.0 / sqrt(x);
+#endif
+}
+AF_HD float rsqrt_of(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return rsqrtf(x);
+#else
+    return 1.0f / sqrtf(x);
+#endif
+}
+
 enum Fam { F_V = 0, F_EV = 1, F_EH = 2, F_C = 3 };
 
 template <class T>

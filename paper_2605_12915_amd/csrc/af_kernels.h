@@ -65,9 +65,11 @@ AF_HD void node_increments(const A& acc, int i, int j, const Pol& pol, T lam0, T
     const Prim<T> Wn = acc.node(FAM, i, j);
     const T rK = pol.rho(Wn.r), pK = pol.pr(Wn.p);
     if (!(rK > T(0)) || !(pK > T(0))) st |= SB_NONPHYS;
-    T c = sqrt(pol.gamma * pK / rK);
-    T Z = rK * c;
-    T iZ = T(1) / Z;
+    // c = sqrt(gamma p / rho) and Z = rho c from one reciprocal square root:
+    // 1 / Z = (gamma p rho)^(-1/2), c = gamma p / Z, Z = gamma p rho / Z
+    const T gp = pol.gamma * pK, q = gp * rK;
+    const T iZ = rsqrt_of(q);
+    const T c = gp * iZ, Z = q * iZ;
     NodeAcc<T> na;
     na.zero();
     node_wedges<FAM>(acc, i, j, na);

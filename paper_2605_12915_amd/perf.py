@@ -27,9 +27,9 @@ import re
 import json
 import os
 
-ALGO_FLOPS_PER_CELL_F64 = 4462
+ALGO_FLOPS_PER_CELL_F64 = 4466
 ALGO_BYTES_PER_CELL_F64 = 256
-ALGO_FLOPS_PER_CELL_ADJ = 14293
+ALGO_FLOPS_PER_CELL_ADJ = 14297
 ALGO_BYTES_PER_CELL_ADJ = 384
 ALGO_BYTES_PER_CELL_F32 = 160      # 16 float planes each way + 4 compensation planes read and written
 HBM_PEAK_GBS = 8000.0
