@@ -40,6 +40,18 @@ AF_HD float rsqrt_of(float x) {
 #endif
 }
 
+// a / b: the correctly rounded quotient in FP64; in FP32 the product with the hardware
+// reciprocal (within 1 ulp; a few instructions against the division's scaled iteration),
+// whose rounding is far inside the FP32 form's stated error; the host builds divide.
+AF_HD double quot(double a, double b) { return a / b; }
+AF_HD float quot(float a, float b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return a * __builtin_amdgcn_rcpf(b);
+#else
+    return a / b;
+#endif
+}
+
 enum Fam { F_V = 0, F_EV = 1, F_EH = 2, F_C = 3 };
 
 template <class T>
@@ -290,7 +302,7 @@ struct PolPert {
             Uc[k] = Ua[k] + T(2.25) * ((Ub[k] - Ua[k]) - sc[k] * T(1.0 / 36.0) - se[k] * T(1.0 / 9.0));
         Prim<T> w;
         w.r = Uc[0];
-        const T ir = T(1) / (r0 + Uc[0]);
+        const T ir = quot(T(1), r0 + Uc[0]);
         w.u = (Uc[1] - u0 * Uc[0]) * ir;
         w.v = (Uc[2] - v0 * Uc[0]) * ir;
         const T uu = u0 + w.u, vv = v0 + w.v;

@@ -173,12 +173,12 @@ AF_HD Prim<T> point_update_f(const A& acc, const D& dinc, int fam, int i, int j,
             T val = q2(xm, xp, ym, yp, g);
             if (var == 0) du = val; else if (var == 1) dv = val; else dp = val;
         }
-        rho_over_c2 = pol.rho(Wf.r) / (pol.gamma * pol.pr(Wf.p));    // 1 / c^2 at the foot
+        rho_over_c2 = quot(pol.rho(Wf.r), pol.gamma * pol.pr(Wf.p));    // 1 / c^2 at the foot
     } else {
         du = dinc.inc(fam, i, j, 0);
         dv = dinc.inc(fam, i, j, 1);
         dp = dinc.inc(fam, i, j, 2);
-        rho_over_c2 = pol.rho(WP.r) / (pol.gamma * pol.pr(WP.p));    // frozen 1 / c^2 at P
+        rho_over_c2 = quot(pol.rho(WP.r), pol.gamma * pol.pr(WP.p));    // frozen 1 / c^2 at P
     }
     return Prim<T>{Wf.r + dp * rho_over_c2, Wf.u + du, Wf.v + dv, Wf.p + dp};
 }
@@ -256,13 +256,13 @@ AF_HD void point_update_pair_f(const A& acc, const D& d0, const D& d1, int fam, 
                 du = q2(xm, xp, ym, yp, g[0]);
                 dv = q2(xm, xp, ym, yp, g[1]);
                 dp = q2(xm, xp, ym, yp, g[2]);
-                rho_over_c2 = pol.rho(Wf.r) / (pol.gamma * pol.pr(Wf.p));
+                rho_over_c2 = quot(pol.rho(Wf.r), pol.gamma * pol.pr(Wf.p));
             } else {
                 const D& dd = t ? d1 : d0;
                 du = dd.inc(fam, i, j, 0);
                 dv = dd.inc(fam, i, j, 1);
                 dp = dd.inc(fam, i, j, 2);
-                rho_over_c2 = pol.rho(WP.r) / (pol.gamma * pol.pr(WP.p));
+                rho_over_c2 = quot(pol.rho(WP.r), pol.gamma * pol.pr(WP.p));
             }
             wr[t] = Prim<T>{Wf.r + dp * rho_over_c2, Wf.u + du, Wf.v + dv, Wf.p + dp};
         }

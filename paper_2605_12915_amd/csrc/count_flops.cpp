@@ -42,6 +42,7 @@ inline bool operator<=(Cnt a, Cnt b) { return a.v <= b.v; }
 inline bool operator!=(Cnt a, Cnt b) { return a.v != b.v; }
 inline Cnt sqrt(Cnt a) { ++g_sqrt; return Cnt(std::sqrt(a.v)); }
 inline Cnt rsqrt_of(Cnt a) { ++g_sqrt; ++g_div; return Cnt(1.0 / std::sqrt(a.v)); }   // a root and a quotient
+inline Cnt quot(Cnt a, Cnt b) { return a / b; }
 inline Cnt fabs(Cnt a) { return Cnt(std::fabs(a.v)); }
 inline Cnt floor(Cnt a) { return Cnt(std::floor(a.v)); }
 
