@@ -48,7 +48,7 @@ __device__ __forceinline__ void diag_wave_reduce(double v[kDiagVals]) {
 __device__ __forceinline__ void diag_node(double v[kDiagVals], double w, double r, double u, double vv, double p,
                                           double gamma) {
     v[4] -= w * r * (log_pos(p) - gamma * log_pos(r));
-    const double cs = sqrt(gamma * p / r);
+    const double gp = gamma * p, cs = gp * rsqrt(gp * r);   // sqrt(gamma p / rho)
     v[5] = fmin(v[5], r);
     v[6] = fmin(v[6], p);
     v[7] = fmax(v[7], sqrt(u * u + vv * vv) + cs);
