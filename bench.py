@@ -276,6 +276,17 @@ def form_adjoint(torch, dev, n, steps, every=20, ndir=8):
     grad()                                   # first use loads torch's own kernels
     xg.grad = None
     t_grad = timed(torch, grad)
+
+    # the same gradient with every state kept (steps x 16 planes: a few GB at 512^2 against
+    # 288 GB of HBM), so that the backward pass recomputes nothing
+    def grad_all():
+        xa = x0.clone().requires_grad_(True)
+        val = J(rollout(xa, st, dt, steps, 1))
+        val.backward()
+        return xa.grad
+
+    ga = grad_all()
+    t_grad_all = timed(torch, grad_all)
     J_of_initial(x0)
     t_fwd_roll = timed(torch, lambda: J_of_initial(x0))
     G = xg.grad.detach()
@@ -308,6 +319,9 @@ def form_adjoint(torch, dev, n, steps, every=20, ndir=8):
            "roofline": roof, "gradient_steps": steps, "checkpoint_every": every,
            "gradient_ms": t_grad * 1e3, "forward_rollout_ms": t_fwd_roll * 1e3,
            "gradient_over_forward_rollout": t_grad / t_fwd_roll,
+           "gradient_every_state_kept_ms": t_grad_all * 1e3,
+           "gradient_every_state_kept_over_forward_rollout": t_grad_all / t_fwd_roll,
+           "gradient_every_state_kept_max_rel_diff": float((ga - G).abs().max() / G.abs().max()),
            "fd_check": {"directions": ndir, "eps": eps, "max_rel_err": max(errs[eps]),
                         "max_err_over_grad_norm": max(norm_errs),
                         "eps_1e-6": {"eps": eps_list[1], "max_rel_err": max(errs[eps_list[1]])},
