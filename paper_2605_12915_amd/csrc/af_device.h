@@ -211,6 +211,23 @@ AF_HD T q2(T xm, T xp, T ym, T yp, const T f[3][3]) {
     return q1(ym, yp, g0, g1, g2);
 }
 
+// FP32: the tensor weights lx[a] ly[b] (lx = (xm, 1 - xm - xp, xp)) times the nodal values,
+// nine products whose weights every evaluation at the same point shares (the compiler
+// forms them once), against sixteen operations per evaluation in the difference form.
+// The FP32 form's values are perturbations about a uniform background, which stays exact
+// (a zero perturbation stays zero); the FP64 path keeps the difference form, exact on
+// constants.
+template <>
+AF_HD float q2<float>(float xm, float xp, float ym, float yp, const float f[3][3]) {
+    const float lx[3] = {xm, 1.0f - xm - xp, xp}, ly[3] = {ym, 1.0f - ym - yp, yp};
+    float s = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) s += (lx[a] * ly[b]) * f[a][b];
+    return s;
+}
+
 template <class T>
 AF_HD void flux_x(const Prim<T>& w, T gm1inv, T F[4]) {
     T E = w.p * gm1inv + T(0.5) * w.r * (w.u * w.u + w.v * w.v);
